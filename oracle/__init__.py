@@ -1,0 +1,186 @@
+"""FP64 CPU oracle of the 2D particle-in-cell space-charge step.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the package smoke check and the
+benchmark's CPU-baseline leg may import this module.  The product path (the
+HIP library and its Python binding) never imports, links or calls it, and it
+shares no code with that path.
+
+The arithmetic lives in ``scpic_oracle.c`` (plain C, FP64, no fused
+multiply-add, OpenMP over particles / target nodes).  This file only builds it
+with gcc and marshals numpy arrays through ctypes.
+
+What each function follows (arXiv:2010.11540):
+  push        Sec. III: transfer map per element, linear (v <- M v) or the kick
+              step of the split thick sextupole (Sec. III-C, potential V).
+  deposit     Sec. IV-A: bilinear (cloud-in-cell) charge assignment to the four
+              nodes of a cell, in 2^-24 fixed-point charge units.
+  potential   open-boundary Poisson solve by convolution with the free-space
+              Green's function -ln r (Hockney's method, cited in Sec. I), as a
+              direct sum over charged nodes.
+  field       E = -grad(u) (Sec. IV-C), by centred differences on the nodes.
+  kick        Sec. IV: transverse kick proportional to the field at the
+              particle times the distance since the previous kick.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "scpic_oracle.c"
+_LIB = _HERE / "liborc.so"
+
+LIN2X2, LIN4X4, SEXT_THIN, SC = 1, 2, 3, 4
+CHARGE_ONE = 1 << 24
+
+_C_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc into oracle/liborc.so."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp")
+        subprocess.run(["gcc", *_C_FLAGS, str(_SRC), "-o", str(tmp), "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists():
+            build()
+        L = ctypes.CDLL(str(_LIB))
+        i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        L.orc_num_threads.restype = i32
+        L.orc_push.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp]
+        L.orc_push.restype = None
+        L.orc_deposit.argtypes = [i64, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp]
+        L.orc_deposit.restype = i64
+        L.orc_green.argtypes = [i32, i32, dbl, dbl]
+        L.orc_green.restype = dbl
+        L.orc_potential.argtypes = [vp, dbl, i32, i32, dbl, dbl, vp]
+        L.orc_potential.restype = None
+        L.orc_field.argtypes = [vp, i32, i32, dbl, dbl, vp, vp]
+        L.orc_field.restype = None
+        L.orc_kick.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp, dbl]
+        L.orc_kick.restype = None
+        L.orc_space_charge.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
+                                       dbl, dbl, vp, vp]
+        L.orc_space_charge.restype = i64
+        L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, vp, vp,
+                                i32]
+        L.orc_track.restype = None
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _grid_args(grid):
+    return (int(grid["nx"]), int(grid["ny"]), float(grid["x_min"]), float(grid["y_min"]),
+            float(grid["dx"]), float(grid["dy"]))
+
+
+def _elements(elements):
+    kind = np.ascontiguousarray(elements["kind"], dtype=np.int32)
+    par = np.ascontiguousarray(elements["p"], dtype=np.float64).reshape(-1, 16)
+    return kind, par
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def push(parts: dict, elements) -> None:
+    """In place: push particles through the non-space-charge elements."""
+    kind, par = _elements(elements)
+    n = parts["x"].shape[0]
+    lib().orc_push(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
+                   _ptr(parts.get("lost")), len(kind), _ptr(kind), _ptr(par))
+
+
+def deposit(parts: dict, grid) -> tuple[np.ndarray, int]:
+    """Charge grid q (int64, nx*ny, 2^24 units per particle) and number deposited.
+    Marks out-of-domain particles lost when parts has a 'lost' array."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    q = np.zeros(nx * ny, dtype=np.int64)
+    n = parts["x"].shape[0]
+    n_in = lib().orc_deposit(n, _ptr(parts["x"]), _ptr(parts["y"]), _ptr(parts.get("lost")),
+                             *_grid_args(grid), _ptr(q))
+    if n_in < 0:
+        raise MemoryError("oracle deposit: allocation failed")
+    return q, int(n_in)
+
+
+def green(di: int, dj: int, dx: float, dy: float) -> float:
+    return lib().orc_green(di, dj, dx, dy)
+
+
+def potential(q: np.ndarray, scale: float, grid) -> np.ndarray:
+    """phi on nodes -1..nx, -1..ny as an (nx+2, ny+2) array."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    q = np.ascontiguousarray(q, dtype=np.int64)
+    phi = np.zeros((nx + 2) * (ny + 2), dtype=np.float64)
+    lib().orc_potential(_ptr(q), float(scale), nx, ny, float(grid["dx"]), float(grid["dy"]),
+                        _ptr(phi))
+    return phi.reshape(nx + 2, ny + 2)
+
+
+def field(phi: np.ndarray, grid) -> tuple[np.ndarray, np.ndarray]:
+    """(ex, ey), each nx*ny row-major."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    phi = _f64(phi)
+    ex = np.zeros(nx * ny)
+    ey = np.zeros(nx * ny)
+    lib().orc_field(_ptr(phi), nx, ny, float(grid["dx"]), float(grid["dy"]), _ptr(ex), _ptr(ey))
+    return ex, ey
+
+
+def solve(q: np.ndarray, scale: float, grid) -> tuple[np.ndarray, np.ndarray]:
+    """Field on the nodes from a charge grid: potential then centred differences."""
+    return field(potential(q, scale, grid), grid)
+
+
+def kick(parts: dict, grid, ex: np.ndarray, ey: np.ndarray, kappa: float) -> None:
+    """In place: gather the node field with the deposit weights, p += kappa * E."""
+    n = parts["x"].shape[0]
+    ex = _f64(ex)
+    ey = _f64(ey)
+    lib().orc_kick(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
+                   _ptr(parts.get("lost")), *_grid_args(grid), _ptr(ex), _ptr(ey), float(kappa))
+
+
+def space_charge(parts: dict, grid, scale: float, kappa: float):
+    """One full space-charge step in place; returns (ex, ey, n_in)."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    ex = np.zeros(nx * ny)
+    ey = np.zeros(nx * ny)
+    n = parts["x"].shape[0]
+    n_in = lib().orc_space_charge(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                                  _ptr(parts["py"]), _ptr(parts.get("lost")), *_grid_args(grid),
+                                  float(scale), float(kappa), _ptr(ex), _ptr(ey))
+    return ex, ey, int(n_in)
+
+
+def track(parts: dict, grid, elements, n_turns: int) -> None:
+    """In place: n_turns through the one-turn element sequence."""
+    kind, par = _elements(elements)
+    n = parts["x"].shape[0]
+    lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
+                    _ptr(parts.get("lost")), *_grid_args(grid), len(kind), _ptr(kind), _ptr(par),
+                    int(n_turns))

@@ -1,0 +1,327 @@
+/*
+ * scpic_oracle.c -- plain, slow, FP64 CPU oracle of the 2D particle-in-cell
+ * space-charge step (push -> charge deposit -> open-boundary Poisson solve ->
+ * field -> gather and kick).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file: it exists so that the tests, the smoke check and the CPU
+ * baseline leg of the benchmark have an independent answer to compare the HIP
+ * path against.  It shares no code, header, table or constant generator with
+ * the HIP library.
+ *
+ * Build:  gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared
+ * (-ffp-contract=off: every expression below is evaluated as written, each
+ *  operation correctly rounded, no fused multiply-add.)
+ *
+ * Conventions (shared by the tests):
+ *   particles   structure of arrays x, px, y, py (m, rad); lost[p] != 0 means
+ *               the particle has left the grid and is frozen.
+ *   grid        nx, ny nodes at x_min + i*dx, y_min + j*dy; node arrays are
+ *               row-major [i*ny + j] (i along x).
+ *   elements    kind[e], par[e*16 + k]:
+ *                 1 LIN2X2   par[0..3] x-block, par[4..7] y-block (row-major)
+ *                 2 LIN4X4   par[0..15] row-major on (x, px, y, py)
+ *                 3 SEXTUPOLE_THIN  par[0] = k2*L
+ *                 4 SPACE_CHARGE    par[0] = kick coefficient kappa
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_LIN2X2 1
+#define ORC_LIN4X4 2
+#define ORC_SEXT_THIN 3
+#define ORC_SC 4
+
+/* Fixed-point charge assignment: 12 fractional bits per axis, so the four
+ * weights of one particle sum to exactly 2^24 charge units. */
+#define ORC_FRAC_ONE 4096
+#define ORC_CHARGE_ONE 16777216.0 /* 2^24 */
+
+typedef struct {
+    int nx, ny;
+    double x_min, y_min, dx, dy;
+    double inv_dx, inv_dy;
+} orc_grid;
+
+static orc_grid make_grid(int nx, int ny, double x_min, double y_min, double dx, double dy)
+{
+    orc_grid g;
+    g.nx = nx;
+    g.ny = ny;
+    g.x_min = x_min;
+    g.y_min = y_min;
+    g.dx = dx;
+    g.dy = dy;
+    g.inv_dx = 1.0 / dx;
+    g.inv_dy = 1.0 / dy;
+    return g;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-particle mechanics (Sec. III): each element is a symplectic map.   */
+/* ------------------------------------------------------------------------ */
+
+/* One element applied to one particle.  A linear element multiplies the
+ * phase-space vector by its transfer matrix (v <- M v).  The thin sextupole is
+ * the kick step of the split thick-sextupole integrator of Sec. III-C with the
+ * drift parts removed: with V = k2 (x^3 - 3 x y^2) / 6 and integrated strength
+ * k2*L, the momenta change by -dV/dx * L and -dV/dy * L. */
+static void push_one(double *x, double *px, double *y, double *py, int kind, const double *m)
+{
+    double X = *x, PX = *px, Y = *y, PY = *py;
+    if (kind == ORC_LIN2X2) {
+        *x = m[0] * X + m[1] * PX;
+        *px = m[2] * X + m[3] * PX;
+        *y = m[4] * Y + m[5] * PY;
+        *py = m[6] * Y + m[7] * PY;
+    } else if (kind == ORC_LIN4X4) {
+        *x = m[0] * X + m[1] * PX + m[2] * Y + m[3] * PY;
+        *px = m[4] * X + m[5] * PX + m[6] * Y + m[7] * PY;
+        *y = m[8] * X + m[9] * PX + m[10] * Y + m[11] * PY;
+        *py = m[12] * X + m[13] * PX + m[14] * Y + m[15] * PY;
+    } else if (kind == ORC_SEXT_THIN) {
+        double k2l = m[0];
+        *px = PX - 0.5 * k2l * (X * X - Y * Y);
+        *py = PY + k2l * X * Y;
+    }
+}
+
+/* Apply the non-space-charge elements in order; lost particles are frozen. */
+void orc_push(int64_t n, double *x, double *px, double *y, double *py, const uint8_t *lost,
+              int n_el, const int32_t *kind, const double *par)
+{
+    int64_t p;
+#pragma omp parallel for schedule(static)
+    for (p = 0; p < n; ++p) {
+        if (lost && lost[p]) continue;
+        for (int e = 0; e < n_el; ++e)
+            if (kind[e] != ORC_SC) push_one(&x[p], &px[p], &y[p], &py[p], kind[e], par + 16 * e);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Charge assignment (Sec. IV-A): cloud-in-cell onto the four nodes of the   */
+/* cell holding the particle, weights bilinear in the position inside it.   */
+/* ------------------------------------------------------------------------ */
+
+/* Cell index and the integer weights of one particle; returns 0 when the
+ * particle is outside the half-open domain [x_min, x_min + (nx-1) dx) x [...]
+ * (a NaN coordinate is outside).  w[0..3] are the weights of nodes (i,j),
+ * (i+1,j), (i,j+1), (i+1,j+1); they are the paper's bilinear fractions rounded
+ * to 12 bits per axis and sum to exactly 2^24. */
+static int cic_weights(const orc_grid *g, double x, double y, int *ci, int *cj, int64_t w[4])
+{
+    double tx = (x - g->x_min) * g->inv_dx;
+    double ty = (y - g->y_min) * g->inv_dy;
+    if (!(tx >= 0.0 && tx < (double)(g->nx - 1))) return 0;
+    if (!(ty >= 0.0 && ty < (double)(g->ny - 1))) return 0;
+    double fi = floor(tx), fj = floor(ty);
+    double fx = tx - fi, fy = ty - fj; /* exact */
+    int64_t a = (int64_t)floor(fx * 4096.0 + 0.5);
+    int64_t b = (int64_t)floor(fy * 4096.0 + 0.5);
+    *ci = (int)fi;
+    *cj = (int)fj;
+    w[0] = (ORC_FRAC_ONE - a) * (ORC_FRAC_ONE - b);
+    w[1] = a * (ORC_FRAC_ONE - b);
+    w[2] = (ORC_FRAC_ONE - a) * b;
+    w[3] = a * b;
+    return 1;
+}
+
+/* Deposit all alive particles into q (int64 charge units, overwritten).
+ * Particles outside the domain are marked lost.  Returns the number of
+ * particles deposited. */
+int64_t orc_deposit(int64_t n, const double *x, const double *y, uint8_t *lost, int nx, int ny,
+                    double x_min, double y_min, double dx, double dy, int64_t *q)
+{
+    orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+    int64_t cells = (int64_t)nx * ny;
+    int nt = orc_num_threads();
+    int64_t *priv = (int64_t *)calloc((size_t)(nt * cells), sizeof(int64_t));
+    int64_t n_in = 0;
+    if (!priv) return -1;
+#pragma omp parallel reduction(+ : n_in)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        int64_t *mine = priv + (int64_t)t * cells;
+        int64_t p;
+#pragma omp for schedule(static)
+        for (p = 0; p < n; ++p) {
+            if (lost && lost[p]) continue;
+            int i, j;
+            int64_t w[4];
+            if (!cic_weights(&g, x[p], y[p], &i, &j, w)) {
+                if (lost) lost[p] = 1;
+                continue;
+            }
+            mine[(int64_t)i * ny + j] += w[0];
+            mine[(int64_t)(i + 1) * ny + j] += w[1];
+            mine[(int64_t)i * ny + j + 1] += w[2];
+            mine[(int64_t)(i + 1) * ny + j + 1] += w[3];
+            n_in += 1;
+        }
+    }
+    for (int64_t c = 0; c < cells; ++c) {
+        int64_t s = 0;
+        for (int t = 0; t < nt; ++t) s += priv[(int64_t)t * cells + c];
+        q[c] = s;
+    }
+    free(priv);
+    return n_in;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Open-boundary Poisson solve (Hockney's free-space Green's function).      */
+/* ------------------------------------------------------------------------ */
+
+/* Antiderivative of ln(x^2 + y^2) in both variables (d2F/dxdy = ln(x^2+y^2)),
+ * for x, y > 0. */
+static double log_antiderivative(double x, double y)
+{
+    return x * y * (log(x * x + y * y) - 3.0) + x * x * atan(y / x) + y * y * atan(x / y);
+}
+
+/* Green's function of the 2D Laplacian normalised so that lap G = -2 pi delta:
+ * G(X, Y) = -ln(r) = -ln(X^2 + Y^2) / 2 at offsets (di*dx, dj*dy) != 0; at the
+ * origin the singular value is replaced by its average over one cell. */
+double orc_green(int di, int dj, double dx, double dy)
+{
+    if (di == 0 && dj == 0) {
+        double a = 0.5 * dx, b = 0.5 * dy;
+        return -log_antiderivative(a, b) / (2.0 * a * b);
+    }
+    double X = di * dx, Y = dj * dy;
+    return -0.5 * log(X * X + Y * Y);
+}
+
+/* Potential phi = G (*) rho by the direct sum over all charged nodes, at the
+ * nodes i = -1..nx, j = -1..ny (one ring of nodes around the grid, needed by
+ * the centred differences of the field).  rho = q * scale.
+ * phi is (nx+2) x (ny+2), row-major, phi[(i+1)*(ny+2) + (j+1)]. */
+void orc_potential(const int64_t *q, double scale, int nx, int ny, double dx, double dy, double *phi)
+{
+    /* G depends only on |di|, |dj| <= nx, ny: tabulate it once. */
+    int gx = nx + 1, gy = ny + 1;
+    double *G = (double *)malloc(sizeof(double) * (size_t)gx * gy);
+    for (int di = 0; di < gx; ++di)
+        for (int dj = 0; dj < gy; ++dj) G[di * gy + dj] = orc_green(di, dj, dx, dy);
+    int64_t ti;
+    int64_t targets = (int64_t)(nx + 2) * (ny + 2);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (ti = 0; ti < targets; ++ti) {
+        int i = (int)(ti / (ny + 2)) - 1;
+        int j = (int)(ti % (ny + 2)) - 1;
+        double s = 0.0;
+        for (int k = 0; k < nx; ++k)
+            for (int l = 0; l < ny; ++l) {
+                int64_t c = q[(int64_t)k * ny + l];
+                if (c == 0) continue;
+                s += G[abs(i - k) * gy + abs(j - l)] * ((double)c * scale);
+            }
+        phi[ti] = s;
+    }
+    free(G);
+}
+
+/* E = -grad(phi) by centred differences at the nodes 0..nx-1, 0..ny-1. */
+void orc_field(const double *phi, int nx, int ny, double dx, double dy, double *ex, double *ey)
+{
+    int sy = ny + 2;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double pxp = phi[(i + 2) * sy + (j + 1)], pxm = phi[i * sy + (j + 1)];
+            double pyp = phi[(i + 1) * sy + (j + 2)], pym = phi[(i + 1) * sy + j];
+            ex[i * ny + j] = -(pxp - pxm) / (2.0 * dx);
+            ey[i * ny + j] = -(pyp - pym) / (2.0 * dy);
+        }
+}
+
+/* Interpolate the node field to each alive particle with the same four
+ * weights as the deposit and kick its momenta: p += kappa * E.  A particle
+ * outside the domain is marked lost instead.  (Sec. IV: the transverse kick is
+ * proportional to the field times the distance since the previous
+ * space-charge location; kappa carries that length and the perveance.) */
+void orc_kick(int64_t n, const double *x, double *px, const double *y, double *py, uint8_t *lost,
+              int nx, int ny, double x_min, double y_min, double dx, double dy, const double *ex,
+              const double *ey, double kappa)
+{
+    orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+    int64_t p;
+#pragma omp parallel for schedule(static)
+    for (p = 0; p < n; ++p) {
+        if (lost && lost[p]) continue;
+        int i, j;
+        int64_t w[4];
+        if (!cic_weights(&g, x[p], y[p], &i, &j, w)) {
+            if (lost) lost[p] = 1;
+            continue;
+        }
+        int64_t c00 = (int64_t)i * ny + j, c10 = c00 + ny, c01 = c00 + 1, c11 = c00 + ny + 1;
+        double exp_ = ((double)w[0] * ex[c00] + (double)w[1] * ex[c10] + (double)w[2] * ex[c01] +
+                       (double)w[3] * ex[c11]) / ORC_CHARGE_ONE;
+        double eyp = ((double)w[0] * ey[c00] + (double)w[1] * ey[c10] + (double)w[2] * ey[c01] +
+                      (double)w[3] * ey[c11]) / ORC_CHARGE_ONE;
+        px[p] += kappa * exp_;
+        py[p] += kappa * eyp;
+    }
+}
+
+/* The whole space-charge step at one location: deposit, potential, field,
+ * kick.  scale converts charge units to the normalised density (1/(2^24 N0)
+ * for N0 initial macro-particles, so the total charge is 1).  ex/ey, when not
+ * NULL, receive the node field.  Returns the number of particles deposited. */
+int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
+                         int nx, int ny, double x_min, double y_min, double dx, double dy,
+                         double scale, double kappa, double *ex_out, double *ey_out)
+{
+    int64_t cells = (int64_t)nx * ny;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)cells);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2));
+    double *ex = ex_out ? ex_out : (double *)malloc(sizeof(double) * (size_t)cells);
+    double *ey = ey_out ? ey_out : (double *)malloc(sizeof(double) * (size_t)cells);
+    int64_t n_in = orc_deposit(n, x, y, lost, nx, ny, x_min, y_min, dx, dy, q);
+    orc_potential(q, scale, nx, ny, dx, dy, phi);
+    orc_field(phi, nx, ny, dx, dy, ex, ey);
+    orc_kick(n, x, px, y, py, lost, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
+    if (!ex_out) free(ex);
+    if (!ey_out) free(ey);
+    free(phi);
+    free(q);
+    return n_in;
+}
+
+/* Track n_turns through the element sequence of one turn: non-space-charge
+ * elements are pushed, each space-charge element runs the full step above with
+ * its own kappa.  The charge scale is 1/(2^24 n): n is the initial particle
+ * count, so lost particles take their charge with them. */
+void orc_track(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost, int nx,
+               int ny, double x_min, double y_min, double dx, double dy, int n_el,
+               const int32_t *kind, const double *par, int n_turns)
+{
+    double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
+    for (int t = 0; t < n_turns; ++t)
+        for (int e = 0; e < n_el; ++e) {
+            if (kind[e] == ORC_SC)
+                orc_space_charge(n, x, px, y, py, lost, nx, ny, x_min, y_min, dx, dy, scale,
+                                 par[16 * e], NULL, NULL);
+            else
+                orc_push(n, x, px, y, py, lost, 1, kind + e, par + 16 * e);
+        }
+}

@@ -1,0 +1,231 @@
+"""Seeded synthetic inputs: beams, grids and ring lattices.
+
+This module only *describes* workloads.  It draws particle coordinates from
+seeded numpy generators and writes lattice element tables; it performs none of
+the space-charge step's arithmetic (no push, deposit, solve or kick), so both
+the HIP path and the CPU oracle can take their inputs from it without sharing
+any of the method.
+
+Workload recipes (stand-ins for the paper's J-PARC Main Ring runs, whose
+lattice and measured beam are not public):
+  * round Gaussian beam, sigma_x = sigma_y = 1 mm, sigma_x' = sigma_y' = 1 mrad
+    (beta = 1 m, alpha = 0 at every space-charge location, matched);
+  * grid of N x N nodes spanning +-6 sigma;
+  * ring of identical segments, each one phase-advance rotation per plane
+    (tunes Q_x, Q_y split evenly over the segments), optional thin sextupoles,
+    one space-charge kick per segment;
+  * kick coefficient set from a target incoherent tune shift with the
+    smooth-focusing Laslett relation for a Gaussian beam (Sec. V, tune-spread
+    estimate): dnu = -K C / (8 pi eps_rms).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# element kinds (same numbering as the C ABI's scpic_element_kind)
+LIN2X2, LIN4X4, SEXT_THIN, SC = 1, 2, 3, 4
+
+ELEMENT_DTYPE = np.dtype([("kind", "<i4"), ("pad", "<i4"), ("p", "<f8", (16,))], align=True)
+assert ELEMENT_DTYPE.itemsize == 136
+
+SEED_BASE = 2010_11540
+
+# proton rest energy [GeV] and classical proton radius [m] (CODATA 2018)
+PROTON_MASS_GEV = 0.93827208816
+PROTON_RADIUS_M = 1.53469857e-18
+
+
+# --------------------------------------------------------------------------
+# grids
+# --------------------------------------------------------------------------
+
+def make_grid(nx: int, ny: int | None = None, half_x: float = 6e-3, half_y: float | None = None,
+              center_x: float = 0.0, center_y: float = 0.0) -> dict:
+    """nx x ny nodes spanning [center - half, center + half] in each plane."""
+    ny = nx if ny is None else ny
+    half_y = half_x if half_y is None else half_y
+    return {
+        "nx": int(nx), "ny": int(ny),
+        "x_min": center_x - half_x, "y_min": center_y - half_y,
+        "dx": 2.0 * half_x / (nx - 1), "dy": 2.0 * half_y / (ny - 1),
+    }
+
+
+# --------------------------------------------------------------------------
+# beams
+# --------------------------------------------------------------------------
+
+def gaussian_beam(n: int, seed: int, sigma_x=1e-3, sigma_px=1e-3, sigma_y=1e-3, sigma_py=1e-3,
+                  lost: bool = True) -> dict:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((4, n))
+    parts = {
+        "x": np.ascontiguousarray(z[0] * sigma_x),
+        "px": np.ascontiguousarray(z[1] * sigma_px),
+        "y": np.ascontiguousarray(z[2] * sigma_y),
+        "py": np.ascontiguousarray(z[3] * sigma_py),
+    }
+    if lost:
+        parts["lost"] = np.zeros(n, dtype=np.uint8)
+    return parts
+
+
+def kv_beam(n: int, seed: int, a=4e-3, b=2e-3, beta_x=1.0, beta_y=1.0, lost: bool = True) -> dict:
+    """Kapchinskij-Vladimirskij beam: uniform on the surface of a 4D ellipsoid,
+    so its x-y projection is a uniform ellipse with semi-axes a, b."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = rng.standard_normal((4, n))
+    u = g / np.linalg.norm(g, axis=0)
+    parts = {
+        "x": np.ascontiguousarray(a * u[0]),
+        "px": np.ascontiguousarray(a / beta_x * u[1]),
+        "y": np.ascontiguousarray(b * u[2]),
+        "py": np.ascontiguousarray(b / beta_y * u[3]),
+    }
+    if lost:
+        parts["lost"] = np.zeros(n, dtype=np.uint8)
+    return parts
+
+
+def uniform_in_box(n: int, seed: int, grid: dict, margin: float = 0.0) -> dict:
+    """Positions uniform over the grid's domain (shrunk by margin cells)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lx = (grid["nx"] - 1) * grid["dx"]
+    ly = (grid["ny"] - 1) * grid["dy"]
+    x = grid["x_min"] + margin * grid["dx"] + rng.random(n) * (lx - 2 * margin * grid["dx"])
+    y = grid["y_min"] + margin * grid["dy"] + rng.random(n) * (ly - 2 * margin * grid["dy"])
+    return {"x": x, "px": rng.standard_normal(n) * 1e-3, "y": y,
+            "py": rng.standard_normal(n) * 1e-3, "lost": np.zeros(n, dtype=np.uint8)}
+
+
+# --------------------------------------------------------------------------
+# lattices
+# --------------------------------------------------------------------------
+
+def elements(n: int) -> np.ndarray:
+    return np.zeros(n, dtype=ELEMENT_DTYPE)
+
+
+def rotation(mu: float, beta: float = 1.0, alpha: float = 0.0) -> np.ndarray:
+    """Courant-Snyder phase-advance matrix of one plane (det = 1)."""
+    c, s = math.cos(mu), math.sin(mu)
+    gamma = (1.0 + alpha * alpha) / beta
+    return np.array([[c + alpha * s, beta * s], [-gamma * s, c - alpha * s]])
+
+
+def lin2x2(mx: np.ndarray, my: np.ndarray) -> np.ndarray:
+    e = elements(1)
+    e["kind"] = LIN2X2
+    e["p"][0, 0:4] = np.asarray(mx, dtype=np.float64).reshape(4)
+    e["p"][0, 4:8] = np.asarray(my, dtype=np.float64).reshape(4)
+    return e
+
+
+def lin4x4(m: np.ndarray) -> np.ndarray:
+    e = elements(1)
+    e["kind"] = LIN4X4
+    e["p"][0, :] = np.asarray(m, dtype=np.float64).reshape(16)
+    return e
+
+
+def sext_thin(k2l: float) -> np.ndarray:
+    e = elements(1)
+    e["kind"] = SEXT_THIN
+    e["p"][0, 0] = k2l
+    return e
+
+
+def sc_kick(kappa: float) -> np.ndarray:
+    e = elements(1)
+    e["kind"] = SC
+    e["p"][0, 0] = kappa
+    return e
+
+
+def block_diag4(mx: np.ndarray, my: np.ndarray) -> np.ndarray:
+    m = np.zeros((4, 4))
+    m[0:2, 0:2] = mx
+    m[2:4, 2:4] = my
+    return m
+
+
+def random_symplectic4(seed: int, scale: float = 0.3) -> np.ndarray:
+    """A coupled 4x4 symplectic matrix exp(J S), S random symmetric."""
+    from scipy.linalg import expm
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.standard_normal((4, 4)) * scale
+    s = a + a.T
+    j = np.array([[0, 1, 0, 0], [-1, 0, 0, 0], [0, 0, 0, 1], [0, 0, -1, 0]], dtype=np.float64)
+    return expm(j @ s)
+
+
+def kappa_for_tune_shift(dnu: float, eps_rms: float, n_kicks: int) -> float:
+    """Kick coefficient per space-charge location giving the incoherent
+    small-amplitude tune shift dnu (< 0) of a round Gaussian beam with rms
+    emittance eps_rms, in the smooth approximation: K C = 8 pi eps |dnu|."""
+    return 8.0 * math.pi * eps_rms * abs(dnu) / n_kicks
+
+
+def ring(qx: float, qy: float, n_seg: int, kappa: float, beta: float = 1.0,
+         four_by_four: bool = False, k2l: float = 0.0, sext_every: int = 0,
+         coupled: np.ndarray | None = None) -> np.ndarray:
+    """One turn of n_seg identical segments: [map; (thin sextupole); SC kick].
+
+    The map advances the phase by 2 pi q / n_seg per plane (LIN2X2, or the same
+    as a block-diagonal LIN4X4).  With sext_every > 0, a thin sextupole of
+    strength k2l follows the map of every sext_every-th segment (1-based).
+    coupled, when given, replaces the map of the first segment (LIN4X4)."""
+    mx = rotation(2.0 * math.pi * qx / n_seg, beta)
+    my = rotation(2.0 * math.pi * qy / n_seg, beta)
+    parts = []
+    for k in range(1, n_seg + 1):
+        if coupled is not None and k == 1:
+            parts.append(lin4x4(coupled))
+        elif four_by_four:
+            parts.append(lin4x4(block_diag4(mx, my)))
+        else:
+            parts.append(lin2x2(mx, my))
+        if sext_every and k % sext_every == 0:
+            parts.append(sext_thin(k2l))
+        if kappa is not None:
+            parts.append(sc_kick(kappa))
+    return np.concatenate(parts)
+
+
+# --------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------
+
+def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
+    """Particles, grid and one-turn lattice of a named workload.
+
+    small      1e4 Gaussian, 64^2 grid over +-6 sigma, 16 segments (2x2 maps,
+               Q = 4.2/4.3), one SC kick per segment, dnu = -0.2; 10 turns.
+    production 1e6 Gaussian, 128^2 grid, 100 block-diagonal 4x4 maps plus 10
+               thin sextupoles (k2L = 5 m^-2) and 100 SC kicks per turn,
+               dnu = -0.2; 100 turns.
+    """
+    eps = 1e-6  # rms emittance (1 mm x 1 mrad)
+    if name == "small":
+        n = 10_000 if n is None else n
+        seed = SEED_BASE + 1 if seed is None else seed
+        grid = make_grid(64)
+        lat = ring(4.2, 4.3, 16, kappa_for_tune_shift(-0.2, eps, 16))
+        turns = 10
+    elif name == "production":
+        n = 1_000_000 if n is None else n
+        seed = SEED_BASE + 2 if seed is None else seed
+        grid = make_grid(128)
+        lat = ring(4.2, 4.3, 100, kappa_for_tune_shift(-0.2, eps, 100), four_by_four=True,
+                   k2l=5.0, sext_every=10)
+        turns = 100
+    else:
+        raise ValueError(f"unknown workload {name!r}")
+    return {"name": name, "parts": gaussian_beam(n, seed), "grid": grid, "lattice": lat,
+            "turns": turns, "n": n, "seed": seed}
+
+
+def copy_parts(parts: dict) -> dict:
+    return {k: v.copy() for k, v in parts.items()}

@@ -1,0 +1,138 @@
+"""Pins of the oracle's open-boundary Poisson solve and field (CPU only).
+
+Normalisation: lap phi = -2 pi rho, E = -grad phi, so a line charge Q has
+E_r = Q / r.  The pins are closed forms and invariants, not a retyped formula.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, signal
+
+from paper_2010_11540_amd import inputs
+from tests.physics import ellipse_field, gaussian_er
+
+
+@pytest.mark.parametrize("dx,dy", [(1e-4, 1e-4), (2e-4, 0.7e-4), (0.05, 0.09)])
+def test_self_cell_green_is_cell_average_by_quadrature(orc, dx, dy):
+    a, b = dx / 2, dy / 2
+    val, err = integrate.dblquad(lambda y, x: -0.5 * math.log(x * x + y * y), 0, a, 0, b,
+                                 epsabs=1e-13, epsrel=1e-12)
+    assert abs(orc.green(0, 0, dx, dy) - val / (a * b)) < 1e-9 * abs(val / (a * b)) + 1e-12
+
+
+def test_green_off_origin_is_minus_log_distance(orc):
+    for di, dj in [(1, 0), (0, 3), (5, 7), (-4, 2)]:
+        r = math.hypot(di * 2e-4, dj * 3e-4)
+        assert abs(orc.green(di, dj, 2e-4, 3e-4) + math.log(r)) < 1e-14
+
+
+def test_direct_sum_equals_linear_convolution(orc):
+    """Independent computation of the same definition: scipy's FFT-based
+    linear convolution of the charge with the tabulated kernel."""
+    nx, ny = 12, 9
+    g = inputs.make_grid(nx, ny, 1.1e-3, 0.8e-3)
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, 1 << 30, size=(nx, ny)).astype(np.int64)
+    scale = 1.0 / q.sum()
+    phi = orc.potential(q.ravel(), scale, g)
+    di = np.arange(-nx, nx + 1)[:, None]
+    dj = np.arange(-ny, ny + 1)[None, :]
+    kern = np.vectorize(lambda a, b: orc.green(int(a), int(b), g["dx"], g["dy"]))(di, dj)
+    full = signal.fftconvolve(q * scale, kern)  # index (i + nx) for target i
+    want = full[nx - 1: 2 * nx + 1, ny - 1: 2 * ny + 1]
+    np.testing.assert_allclose(phi, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+
+
+def _gaussian_field_error(orc, n, sigma=1e-3):
+    g = inputs.make_grid(n, n, 6e-3)
+    xs = g["x_min"] + np.arange(n) * g["dx"]
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    q = np.round(np.exp(-(X ** 2 + Y ** 2) / (2 * sigma ** 2)) * 2.0 ** 40).astype(np.int64)
+    ex, ey = orc.solve(q.ravel(), 1.0 / q.sum(), g)
+    ex, ey = ex.reshape(n, n), ey.reshape(n, n)
+    R = np.hypot(X, Y)
+    m = (R > 0) & (R < 4 * sigma)
+    er = (X * ex + Y * ey) / np.where(R > 0, R, 1)
+    et = (-Y * ex + X * ey) / np.where(R > 0, R, 1)
+    ref = gaussian_er(R, sigma)
+    return np.abs(er - ref)[m].max() / ref[m].max(), np.abs(et)[m].max() / ref[m].max()
+
+
+def test_round_gaussian_field_closed_form_second_order(orc):
+    """E_r = (1 - exp(-r^2/2 sigma^2)) / r, converging at second order in the
+    grid spacing (error ratio ~4 per halving)."""
+    e32, t32 = _gaussian_field_error(orc, 32)
+    e64, t64 = _gaussian_field_error(orc, 64)
+    e128, t128 = _gaussian_field_error(orc, 128)
+    assert e128 < 3e-3
+    assert 3.5 < e32 / e64 < 4.5 and 3.5 < e64 / e128 < 4.5
+    assert t128 < 5e-4
+
+
+def test_uniform_ellipse_field_is_linear_inside_on_anisotropic_grid(orc):
+    """Uniform ellipse (a, b): E_x = 2x/(a(a+b)), E_y = 2y/(b(a+b)) inside; the
+    grid has dx != dy and nx != ny so that any swapped axis shows."""
+    nx, ny, a, b = 96, 64, 3e-3, 1.5e-3
+    g = inputs.make_grid(nx, ny, 4.5e-3, 2.5e-3)
+    xs = g["x_min"] + np.arange(nx) * g["dx"]
+    ys = g["y_min"] + np.arange(ny) * g["dy"]
+    off = (np.arange(8) + 0.5) / 8 - 0.5
+    frac = np.zeros((nx, ny))
+    for ox in off:
+        for oy in off:
+            X, Y = np.meshgrid(xs + ox * g["dx"], ys + oy * g["dy"], indexing="ij")
+            frac += (X / a) ** 2 + (Y / b) ** 2 < 1
+    q = np.round(frac / 64 * 2.0 ** 32).astype(np.int64)
+    ex, ey = orc.solve(q.ravel(), 1.0 / q.sum(), g)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    inside = (X / a) ** 2 + (Y / b) ** 2 < 0.49
+    rx, ry = ellipse_field(X, Y, a, b)
+    scale = np.abs(ry[inside]).max()
+    assert np.abs(ex.reshape(nx, ny) - rx)[inside].max() < 2e-3 * scale
+    assert np.abs(ey.reshape(nx, ny) - ry)[inside].max() < 2e-3 * scale
+
+
+def _one_step_kicks(orc, parts, g):
+    p = {k: v.copy() for k, v in parts.items()}
+    p["px"][:] = 0.0
+    p["py"][:] = 0.0
+    n = p["x"].shape[0]
+    orc.space_charge(p, g, 1.0 / ((1 << 24) * n), 1.0)
+    return p["px"], p["py"]
+
+
+def test_single_particle_feels_no_self_force(orc):
+    g = inputs.make_grid(32)
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        x = rng.uniform(-5e-3, 5e-3)
+        y = rng.uniform(-5e-3, 5e-3)
+        kx, ky = _one_step_kicks(orc, {"x": np.array([x]), "px": np.zeros(1),
+                                       "y": np.array([y]), "py": np.zeros(1)}, g)
+        # a unit charge one cell away would feel 1/dx ~ 2.6e3
+        assert abs(kx[0]) < 1e-9 and abs(ky[0]) < 1e-9
+
+
+def test_total_momentum_is_conserved(orc):
+    """Same weights for deposit and gather plus an even Green's function: the
+    kicks sum to zero (Newton's third law on the grid)."""
+    g = inputs.make_grid(48, 40, 5e-3, 4e-3)
+    p = inputs.gaussian_beam(3000, 31, sigma_x=1.3e-3, sigma_y=0.9e-3)
+    kx, ky = _one_step_kicks(orc, p, g)
+    alive = p["lost"] == 0
+    assert abs(kx[alive].sum()) < 1e-10 * np.abs(kx).sum()
+    assert abs(ky[alive].sum()) < 1e-10 * np.abs(ky).sum()
+
+
+def test_two_particles_repel_antisymmetrically_with_inverse_distance(orc):
+    g = inputs.make_grid(128, 128, 6e-3)
+    d = 64 * g["dx"]
+    x = np.array([-d / 2, d / 2])
+    y = np.array([0.0, 0.0])
+    kx, ky = _one_step_kicks(orc, {"x": x, "px": np.zeros(2), "y": y, "py": np.zeros(2)}, g)
+    assert abs(kx[0] + kx[1]) < 1e-12 * abs(kx[1])
+    assert kx[1] > 0  # repulsive (like charges push apart)
+    # each particle carries half of the unit total charge
+    assert abs(kx[1] - 0.5 / d) < 1e-3 * 0.5 / d
+    assert abs(ky[0]) < 1e-9 * abs(kx[0])
