@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the 2D PIC space-charge step on one MI355X.
+
+A step is one pass of the whole hot path over the beam: kick with the field
+of the previous space-charge location, push through the ring elements up to
+the next one, deposit the charge, solve the open-boundary Poisson equation
+and form the field.  The default workload is the production shape: 1e6
+Gaussian particles, a 128 x 128 grid over +-6 sigma, one turn = 100
+block-diagonal 4x4 transfer maps, 10 thin sextupoles and 100 space-charge
+steps, all in FP64.  Inputs are seeded synthetic data resident in HBM before
+the timed region starts.
+
+Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
+(the fused particle pass, timed live with HIP events on the library's stream)
+and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 64  # read + write x, px, y, py in FP64
+PROFILE_TRAFFIC = ROOT / "profiles" / "pass_traffic_production.json"
+PASS_SOURCE = ROOT / "paper_2010_11540_amd" / "csrc" / "particles.hip"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed SC steps (multiple of steps/turn)")
+    ap.add_argument("--warmup", type=int, default=200, help="untimed SC steps before timing")
+    ap.add_argument("--workload", default="production", choices=["production", "small"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
+    ap.add_argument("--pass-threads", type=int, default=0)
+    ap.add_argument("--pass-blocks", type=int, default=0)
+    ap.add_argument("--pass-reps", type=int, default=200, help="standalone pass launches timed")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
+                    help="wall-clock budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    return ap.parse_args()
+
+
+def source_digest() -> str:
+    return hashlib.sha256(PASS_SOURCE.read_bytes()).hexdigest()[:16]
+
+
+def measured_traffic(n_particles: int):
+    """HBM bytes per pass launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source and this particle count."""
+    try:
+        d = json.loads(PROFILE_TRAFFIC.read_text())
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != source_digest() or d.get("particles") != n_particles:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, seconds: float):
+    """The oracle on the host cores: the production lattice's first space-charge
+    steps on the full beam, repeated until `seconds` of wall time."""
+    import numpy as np
+
+    import oracle
+    from paper_2010_11540_amd import inputs
+
+    lat = w["lattice"]
+    sc_idx = np.nonzero(lat["kind"] == inputs.SC)[0]
+    chunk_steps = min(5, len(sc_idx))
+    chunk = lat[: sc_idx[chunk_steps - 1] + 1]
+    parts = inputs.copy_parts(w["parts"])
+    oracle.lib()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.track(parts, w["grid"], chunk, 1)
+        steps += chunk_steps
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {
+        "value": w["n"] * steps / el,
+        "unit": "particle-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} SC steps (first {chunk_steps} segments of the turn, repeated) on all "
+                  f"{w['n']} particles of the {w['name']} workload, {el:.1f} s wall",
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
+              "the space-charge loop is not sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_11540_amd import inputs, scpic
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = inputs.workload(args.workload)
+    lat = w["lattice"]
+    steps_per_turn = int((lat["kind"] == inputs.SC).sum())
+    if args.steps % steps_per_turn or args.warmup % steps_per_turn:
+        print(f"--steps and --warmup must be multiples of {steps_per_turn} (one turn)",
+              file=sys.stderr)
+        sys.exit(2)
+    n = w["n"]
+    ctx = scpic.Context(w["grid"], args.precision)
+    if args.no_graph:
+        ctx.set_option(scpic.OPT_USE_GRAPH, 0)
+    if args.pass_threads:
+        ctx.set_option(scpic.OPT_PASS_THREADS, args.pass_threads)
+    if args.pass_blocks:
+        ctx.set_option(scpic.OPT_PASS_BLOCKS, args.pass_blocks)
+    d = scpic.to_device(w["parts"])
+    torch.cuda.synchronize()
+
+    if args.warmup:
+        ctx.track(d, lat, args.warmup // steps_per_turn)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.track(d, lat, args.steps // steps_per_turn)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    print(f"[bench] timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
+          file=sys.stderr, flush=True)
+    seconds = wall
+    value = n * args.steps / seconds
+    alive = int((d["lost"] == 0).sum().item())
+
+    # dominant kernel: the fused pass (kick + 4x4 map + deposit), timed alone
+    # on the same stream over a copy of the beam
+    d2 = {k: v.clone() for k, v in d.items()}
+    one_map = lat[lat["kind"] == inputs.LIN4X4][:1]
+    kappa = float(lat["p"][lat["kind"] == inputs.SC][0, 0])
+    scale = 1.0 / ((1 << 24) * n)
+    for _ in range(5):
+        ctx.pass_(d2, True, kappa, one_map, True)
+        ctx.reduce_solve(scale)
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for _ in range(args.pass_reps):
+        ctx.pass_(d2, True, kappa, one_map, True)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    pass_us = p0.elapsed_time(p1) * 1e3 / args.pass_reps
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.pass_reps):
+        ctx.reduce_solve(scale)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    grid_us = g0.elapsed_time(g1) * 1e3 / args.pass_reps
+    achieved = BYTES_PER_PARTICLE_STEP * n / (pass_us * 1e-6) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_pass<double,kick,deposit> (gather+kick, 4x4 map, CIC deposit, flush)",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(n),
+        "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE_STEP * n,
+        "avg_launch_us": round(pass_us, 3),
+        "grid_phase_us": round(grid_us, 3),
+    }
+    del d2
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": "particle-steps/s (push+deposit+solve+kick)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": seconds * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 coords / f32 field",
+        "data": "synthetic",
+        "config": {
+            "workload": ("production 2D PIC: 1e6 Gaussian particles, 128x128 grid, per turn 100 "
+                         "4x4 maps + 10 thin sextupoles + 100 SC steps"
+                         if args.workload == "production" else
+                         "small 2D PIC: 1e4 Gaussian particles, 64x64 grid, 16 SC steps/turn"),
+            "particles": n,
+            "grid": f"{w['grid']['nx']}x{w['grid']['ny']}",
+            "sc_steps_per_turn": steps_per_turn,
+            "precision": args.precision,
+            "graph": not args.no_graph,
+            "alive_after": alive,
+            "gpu_event_ms": round(gpu_ms, 3),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * scpic.h -- C ABI of libscpic, a gfx950 (MI355X) library for the per-step 2D
+ * particle-in-cell space-charge loop of a proton ring (arXiv:2010.11540):
+ *
+ *   push    particles through the ring's elements             (Sec. III)
+ *   deposit charge on a transverse grid of nodes              (Sec. IV-A)
+ *   solve   the 2D open-boundary Poisson equation for E       (Sec. IV, eq. poisson3D;
+ *           Hockney's free-space Green's-function method, cited in Sec. I)
+ *   kick    interpolate E to the particles, kick the momenta  (Sec. IV, transverse kick)
+ *
+ * Conventions
+ *   - Every pointer named "device" is HIP device memory owned by the caller;
+ *     the library never frees it.  Pointers named "host" are read during the
+ *     call only.
+ *   - Every call is asynchronous on the context's stream (see scpic_create /
+ *     scpic_set_stream): it returns after enqueuing work, and results are valid
+ *     once that stream has been synchronised.
+ *   - Invalid arguments return SCPIC_EINVAL before any memory is touched and
+ *     before anything is enqueued.  No C++ exception crosses the ABI.  The
+ *     message of the last error of the calling thread is scpic_last_error().
+ *   - A context serves one host thread at a time.
+ *
+ * Units and normalisation
+ *   Particles carry (x, px, y, py): positions in m, px, py the transverse
+ *   momenta normalised to the reference momentum (rad).  Charge is counted in
+ *   fixed-point units of 2^-24 of one macro-particle.  The potential solves
+ *   lap(phi) = -2 pi rho with the free-space Green's function G = -ln(r), so
+ *   a unit line charge has E_r = 1/r; a space-charge kick is p += kappa * E,
+ *   where kappa carries the perveance, the 1/gamma^3 factor of the paper's
+ *   long-bunch approximation (Sec. IV, eq. pot2) and the distance since the
+ *   previous kick (Sec. IV, transverse kick).
+ */
+#ifndef SCPIC_H
+#define SCPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef int32_t scpic_status;
+#define SCPIC_OK 0
+#define SCPIC_EINVAL (-1)      /* invalid argument; nothing touched */
+#define SCPIC_ENOMEM (-2)      /* device allocation failed (scpic_create only) */
+#define SCPIC_EHIP (-3)        /* a HIP runtime call failed */
+#define SCPIC_EUNSUPPORTED (-4) /* valid but unsupported shape (e.g. grid size) */
+
+/* ---- precision forms --------------------------------------------------- */
+/* SCPIC_FP64:  every step in FP64 (fields are double arrays).
+ * SCPIC_MIXED: coordinates, maps and kick accumulation FP64; the charge grid
+ *              is exact fixed point as in FP64; the Poisson solve, the field
+ *              and its interpolation are FP32 (fields are float arrays). */
+#define SCPIC_FP64 0
+#define SCPIC_MIXED 1
+
+/* ---- grid -------------------------------------------------------------- */
+/* nx x ny nodes at (x_min + i dx, y_min + j dy); node arrays are row-major,
+ * index i*ny + j (i along x).  A particle belongs to the domain when
+ * 0 <= (x - x_min) * (1/dx) < nx - 1 and likewise in y (each product and the
+ * reciprocal evaluated in FP64, correctly rounded); a NaN coordinate does not.
+ * Supported: nx, ny powers of two in [8, 256] and nx * ny <= 16384. */
+typedef struct {
+    int32_t nx, ny;
+    double x_min, y_min, dx, dy;
+} scpic_grid;
+
+/* ---- particles --------------------------------------------------------- */
+/* Structure of arrays, n entries each, device, contiguous FP64.
+ * lost (device, n bytes, may be NULL): nonzero marks a particle that has left
+ * the grid domain at a deposit or kick; a lost particle is frozen (no push,
+ * kick or deposit) and keeps its last coordinates.  With lost == NULL,
+ * particles outside the domain simply take no part in deposit and kick. */
+typedef struct {
+    double *x, *px, *y, *py;
+    uint8_t *lost;
+    int64_t n;
+} scpic_particles;
+
+/* ---- lattice elements (Sec. III) --------------------------------------- */
+/* kind:
+ *   SCPIC_EL_LIN2X2     p[0..3] x-plane matrix on (x, px), p[4..7] y-plane
+ *                       matrix on (y, py), both row-major: v <- M v
+ *   SCPIC_EL_LIN4X4     p[0..15] row-major matrix on (x, px, y, py)
+ *   SCPIC_EL_SEXT_THIN  p[0] = k2*L: the kick step of the split thick
+ *                       sextupole (Sec. III-C) with V = k2 (x^3 - 3 x y^2)/6:
+ *                       px -= (k2L/2)(x^2 - y^2),  py += k2L x y
+ *   SCPIC_EL_SC         p[0] = kappa: a space-charge location (deposit,
+ *                       solve and kick with coefficient kappa)
+ * Linear maps are evaluated as written in row order, left to right, with no
+ * fused multiply-add, so a push is bit-identical to the same sums in IEEE
+ * FP64.  sizeof(scpic_element) == 136. */
+#define SCPIC_EL_LIN2X2 1
+#define SCPIC_EL_LIN4X4 2
+#define SCPIC_EL_SEXT_THIN 3
+#define SCPIC_EL_SC 4
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double p[16];
+} scpic_element;
+
+typedef struct scpic_ctx scpic_ctx;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t scpic_version(void);
+
+/* Message of the calling thread's last error ("" if none).  The pointer stays
+ * valid until the thread's next scpic call. */
+const char *scpic_last_error(void);
+
+/* Create a context for one grid geometry and precision form on the current
+ * HIP device.  It allocates every workspace (per-block charge partials, FFT
+ * spectra, the Green's-function spectrum and the internal field); no call made
+ * afterwards allocates device memory.  hip_stream: the hipStream_t to enqueue
+ * on (NULL = the null stream).  The Green's-function spectrum is computed
+ * here, once. */
+scpic_status scpic_create(scpic_ctx **out, const scpic_grid *grid, int32_t precision,
+                          void *hip_stream);
+
+/* Free a context's workspaces (synchronises its stream first).  NULL is a no-op. */
+scpic_status scpic_destroy(scpic_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+scpic_status scpic_set_stream(scpic_ctx *ctx, void *hip_stream);
+
+/* Push the particles through elements[0..n_el) in order (host array).
+ * SCPIC_EL_SC entries are skipped.  Lost particles are not moved. */
+scpic_status scpic_push(scpic_ctx *ctx, const scpic_particles *parts,
+                        const scpic_element *elements, int32_t n_el);
+
+/* Cloud-in-cell charge deposit (Sec. IV-A).  Each particle in the domain adds
+ * to the four nodes of its cell the integer weights
+ *   (4096-a)(4096-b), a(4096-b), (4096-a)b, ab   at (i,j), (i+1,j), (i,j+1), (i+1,j+1),
+ * with t = (x - x_min)*(1/dx), i = floor(t), a = floor((t-i)*4096 + 0.5) (all
+ * FP64) and likewise b in y: the paper's bilinear fractions rounded to 12 bits
+ * per axis, summing to exactly 2^24 per particle.
+ * rho (device, nx*ny int64) is overwritten with the exact integer sums; the
+ * result does not depend on particle order or launch shape.  Particles outside
+ * the domain are marked lost.  n_in (device, one int64, may be NULL) receives
+ * the number of particles deposited. */
+scpic_status scpic_deposit(scpic_ctx *ctx, const scpic_particles *parts, int64_t *rho,
+                           int64_t *n_in);
+
+/* Open-boundary field of a charge grid: the potential is the linear
+ * convolution of rho*scale with G(X,Y) = -ln(X^2+Y^2)/2 over node offsets
+ * (G(0,0) = the average of G over one cell), taken by a zero-padded
+ * 2nx x 2ny FFT convolution; the field is the centred difference
+ *   ex = -(phi[i+1][j] - phi[i-1][j]) / (2 dx),  ey likewise,
+ * at the nodes 0..nx-1 x 0..ny-1 (both evaluated spectrally).
+ * rho: device, nx*ny int64.  ex, ey: device, nx*ny, double (SCPIC_FP64) or
+ * float (SCPIC_MIXED), row-major. */
+scpic_status scpic_solve(scpic_ctx *ctx, const int64_t *rho, double scale, void *ex, void *ey);
+
+/* Interpolate the node field to each particle with the same four weights as
+ * the deposit (divided by 2^24) and kick: px += kappa*Ex, py += kappa*Ey.
+ * ex, ey: device, as produced by scpic_solve for this context.  Lost particles
+ * are skipped; particles outside the domain are marked lost. */
+scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void *ex,
+                        const void *ey, double kappa);
+
+/* Track n_turns through the one-turn sequence turn[0..n_el) (host array):
+ * non-SC elements are pushed in order; at each SCPIC_EL_SC element the beam's
+ * charge is deposited, the field solved with scale 1/(2^24 * parts->n) (the
+ * charge of lost particles leaves with them) and every particle kicked with
+ * that element's kappa.  Equivalent to the sequence of scpic_push /
+ * scpic_deposit / scpic_solve / scpic_kick calls, fused: each kick, the
+ * following push and the next deposit run as one pass over the particles, and
+ * one turn runs as one captured HIP graph.  Turn graphs are cached per
+ * (particle arrays, lattice); at most 8 are kept. */
+scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scpic_element *turn,
+                         int32_t n_el, int32_t n_turns);
+
+/* Options (scpic_set_option):
+ *   SCPIC_OPT_USE_GRAPH      1 (default): scpic_track replays one HIP graph
+ *                            per turn; 0: it launches the same kernels directly.
+ *   SCPIC_OPT_PASS_BLOCKS    workgroups of the particle pass (0 = automatic:
+ *                            one per compute unit).
+ *   SCPIC_OPT_PASS_THREADS   threads per workgroup of the particle pass
+ *                            (256, 512 or 1024; default 1024). */
+#define SCPIC_OPT_USE_GRAPH 1
+#define SCPIC_OPT_PASS_BLOCKS 2
+#define SCPIC_OPT_PASS_THREADS 3
+scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value);
+
+/* Fused particle pass, one launch: optionally kick with the context's
+ * internal field (kappa; skipped when kick == 0), push through
+ * elements[0..n_el) (at most 12, no SC entries), then optionally deposit into
+ * the context's per-block charge partials (deposit != 0).  This is one step
+ * of scpic_track exposed for timing; scpic_pass followed by scpic_reduce_solve
+ * completes the step. */
+scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t kick, double kappa,
+                        const scpic_element *elements, int32_t n_el, int32_t deposit);
+
+/* Grid phase of one step: sum the per-block partials of the last depositing
+ * scpic_pass, solve with the given scale into the context's internal field. */
+scpic_status scpic_reduce_solve(scpic_ctx *ctx, double scale);
+
+/* Copy the context's internal field (written by scpic_track /
+ * scpic_reduce_solve) to ex, ey (device; double or float per precision). */
+scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCPIC_H */

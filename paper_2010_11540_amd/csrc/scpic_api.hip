@@ -1,0 +1,693 @@
+// Host side of libscpic: the C ABI declared in include/scpic.h.  Contexts own
+// every workspace (allocated once in scpic_create); calls validate their
+// arguments, then enqueue kernels on the context's stream.  scpic_track turns
+// the one-turn element sequence into a schedule of fused particle passes and
+// grid solves and replays it as a captured HIP graph per turn.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "scpic_internal.h"
+
+using namespace scpic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+scpic_status fail(scpic_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+scpic_status fail_hip(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SCPIC_EHIP;
+}
+
+#define SCPIC_HIP_TRY(expr, what)                  \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return fail_hip(e_, what); \
+    } while (0)
+
+bool is_pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+// One launch of the particle pass, as scheduled by scpic_track.
+struct PassOp {
+    bool kick;
+    double kappa;
+    PassElements els;
+    bool deposit;
+};
+
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+}  // namespace
+
+struct scpic_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    scpic_grid grid{};
+    GridGeom geom{};
+    bool mixed = false;
+    int n_cu = 0;
+    int max_blocks = 0;
+    int pass_blocks = 0;  // 0 = automatic
+    int pass_threads = 1024;
+    bool use_graph = true;
+    int last_deposit_blocks = 0;
+
+    DepositTarget dep{};
+    int64_t *q = nullptr;
+    int64_t *n_in = nullptr;
+    SolveWorkspace sw{};
+    void *ex = nullptr, *ey = nullptr;
+
+    std::vector<void *> allocations;
+    std::vector<GraphEntry> graphs;
+    uint64_t use_counter = 0;
+};
+
+namespace {
+
+size_t field_elem_size(const scpic_ctx *c) { return c->mixed ? sizeof(float) : sizeof(double); }
+
+scpic_status dev_alloc(scpic_ctx *c, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    c->allocations.push_back(*p);
+    return SCPIC_OK;
+}
+
+void free_all(scpic_ctx *c)
+{
+    for (auto &g : c->graphs)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    for (void *p : c->allocations) hipFree(p);
+    c->allocations.clear();
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+    c->capture_stream = nullptr;
+}
+
+scpic_status check_ctx(const scpic_ctx *c)
+{
+    if (!c) return fail(SCPIC_EINVAL, "ctx is NULL");
+    return SCPIC_OK;
+}
+
+scpic_status check_parts(const scpic_particles *p)
+{
+    if (!p) return fail(SCPIC_EINVAL, "particles is NULL");
+    if (p->n < 0) return fail(SCPIC_EINVAL, "particle count is negative");
+    if (p->n > 0 && (!p->x || !p->px || !p->y || !p->py))
+        return fail(SCPIC_EINVAL, "a particle coordinate pointer is NULL");
+    return SCPIC_OK;
+}
+
+ParticlePtrs to_ptrs(const scpic_particles *p)
+{
+    ParticlePtrs r;
+    r.x = p->x;
+    r.px = p->px;
+    r.y = p->y;
+    r.py = p->py;
+    r.lost = p->lost;
+    r.n = p->n;
+    return r;
+}
+
+int blocks_for(const scpic_ctx *c, int64_t n, bool deposit)
+{
+    if (n <= 0) return 0;
+    const int64_t need = (n + c->pass_threads - 1) / c->pass_threads;
+    const int64_t cap = deposit ? (c->pass_blocks > 0 ? c->pass_blocks : c->n_cu)
+                                : (int64_t)c->n_cu * 8;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, std::min<int64_t>(cap, c->max_blocks)));
+}
+
+// Non-SC elements of a host array, validated.
+scpic_status collect_elements(const scpic_element *els, int32_t n_el,
+                              std::vector<const scpic_element *> &out, bool allow_sc)
+{
+    if (n_el < 0) return fail(SCPIC_EINVAL, "element count is negative");
+    if (n_el > 0 && !els) return fail(SCPIC_EINVAL, "elements pointer is NULL");
+    for (int i = 0; i < n_el; ++i) {
+        const int k = els[i].kind;
+        if (k != SCPIC_EL_LIN2X2 && k != SCPIC_EL_LIN4X4 && k != SCPIC_EL_SEXT_THIN &&
+            k != SCPIC_EL_SC)
+            return fail(SCPIC_EINVAL, "element " + std::to_string(i) + " has unknown kind " +
+                                          std::to_string(k));
+        if (k == SCPIC_EL_SC && !allow_sc) continue;
+        out.push_back(&els[i]);
+    }
+    return SCPIC_OK;
+}
+
+PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, size_t end)
+{
+    PassElements pe;
+    std::memset(&pe, 0, sizeof(pe));
+    pe.n_el = (int32_t)(end - begin);
+    for (size_t i = begin; i < end; ++i) {
+        pe.kind[i - begin] = v[i]->kind;
+        std::memcpy(pe.p[i - begin], v[i]->p, sizeof(double) * 16);
+    }
+    return pe;
+}
+
+// A run of non-SC elements between space-charge locations as one or more
+// passes: the first carries the pending kick, the last the deposit.
+void emit_segment(std::vector<PassOp> &ops, bool kick, double kappa,
+                  const std::vector<const scpic_element *> &els, bool deposit)
+{
+    const size_t n = els.size();
+    size_t at = 0;
+    bool first = true;
+    do {
+        const size_t end = std::min(n, at + (size_t)kMaxPassElements);
+        PassOp op;
+        op.kick = first && kick;
+        op.kappa = op.kick ? kappa : 0.0;
+        op.els = pack(els, at, end);
+        op.deposit = (end == n) && deposit;
+        ops.push_back(op);
+        first = false;
+        at = end;
+    } while (at < n);
+}
+
+scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
+                          const PassOp &op, const void *ex, const void *ey)
+{
+    const int blocks = blocks_for(c, parts->n, op.deposit);
+    hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, ex, ey, op.kappa,
+                               op.els, op.deposit, c->dep, blocks, c->pass_threads);
+    if (e != hipSuccess) return fail_hip(e, "particle pass launch");
+    if (op.deposit) c->last_deposit_blocks = blocks;
+    return SCPIC_OK;
+}
+
+scpic_status enqueue_grid_phase(scpic_ctx *c, hipStream_t s, double scale)
+{
+    hipError_t e = launch_reduce(s, c->dep, c->last_deposit_blocks, c->grid.nx, c->grid.ny, c->q,
+                                 nullptr);
+    if (e != hipSuccess) return fail_hip(e, "reduce launch");
+    e = launch_solve(s, c->sw, c->q, scale, c->ex, c->ey);
+    if (e != hipSuccess) return fail_hip(e, "solve launch");
+    return SCPIC_OK;
+}
+
+// Schedule of one turn.  The kick of a space-charge location is applied at
+// the start of the next pass (positions are unchanged between the deposit and
+// that kick, so this equals kicking at the location).  first_turn: no kick is
+// pending from a previous turn and the trailing elements after the last SC
+// location have not been pushed yet.
+void build_turn(const std::vector<const scpic_element *> &all, bool first_turn,
+                std::vector<PassOp> &ops, bool &any_sc, double &last_kappa,
+                std::vector<const scpic_element *> &trailing)
+{
+    std::vector<size_t> sc;
+    for (size_t i = 0; i < all.size(); ++i)
+        if (all[i]->kind == SCPIC_EL_SC) sc.push_back(i);
+    any_sc = !sc.empty();
+    trailing.clear();
+    if (!any_sc) {
+        emit_segment(ops, false, 0.0, all, false);
+        return;
+    }
+    for (size_t i = sc.back() + 1; i < all.size(); ++i) trailing.push_back(all[i]);
+    last_kappa = all[sc.back()]->p[0];
+    std::vector<const scpic_element *> seg;
+    if (!first_turn) seg = trailing;
+    for (size_t i = 0; i < sc[0]; ++i) seg.push_back(all[i]);
+    emit_segment(ops, !first_turn, last_kappa, seg, true);
+    for (size_t k = 1; k < sc.size(); ++k) {
+        seg.clear();
+        for (size_t i = sc[k - 1] + 1; i < sc[k]; ++i) seg.push_back(all[i]);
+        emit_segment(ops, true, all[sc[k - 1]]->p[0], seg, true);
+    }
+}
+
+scpic_status enqueue_ops(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
+                         const std::vector<PassOp> &ops, double scale)
+{
+    for (const PassOp &op : ops) {
+        scpic_status st = enqueue_pass(c, s, parts, op, c->ex, c->ey);
+        if (st) return st;
+        if (op.deposit) {
+            st = enqueue_grid_phase(c, s, scale);
+            if (st) return st;
+        }
+    }
+    return SCPIC_OK;
+}
+
+std::vector<unsigned char> graph_key(const scpic_ctx *c, const scpic_particles *p,
+                                     const std::vector<PassOp> &ops)
+{
+    std::vector<unsigned char> k;
+    auto put = [&k](const void *d, size_t n) {
+        const unsigned char *b = (const unsigned char *)d;
+        k.insert(k.end(), b, b + n);
+    };
+    put(p, sizeof(*p));
+    put(&c->pass_blocks, sizeof(c->pass_blocks));
+    put(&c->pass_threads, sizeof(c->pass_threads));
+    for (const PassOp &op : ops) {
+        put(&op.kick, sizeof(op.kick));
+        put(&op.kappa, sizeof(op.kappa));
+        put(&op.deposit, sizeof(op.deposit));
+        put(&op.els.n_el, sizeof(op.els.n_el));
+        put(op.els.kind, sizeof(int32_t) * op.els.n_el);
+        put(op.els.p, sizeof(double) * 16 * op.els.n_el);
+    }
+    return k;
+}
+
+scpic_status get_turn_graph(scpic_ctx *c, const scpic_particles *parts,
+                            const std::vector<PassOp> &ops, double scale, hipGraphExec_t *out)
+{
+    std::vector<unsigned char> key = graph_key(c, parts, ops);
+    key.insert(key.end(), (unsigned char *)&scale, (unsigned char *)&scale + sizeof(scale));
+    for (auto &g : c->graphs)
+        if (g.key == key) {
+            g.last_use = ++c->use_counter;
+            *out = g.exec;
+            return SCPIC_OK;
+        }
+    if (!c->capture_stream) SCPIC_HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    SCPIC_HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal),
+                  "hipStreamBeginCapture");
+    const int saved_blocks = c->last_deposit_blocks;
+    scpic_status st = enqueue_ops(c, c->capture_stream, parts, ops, scale);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+    c->last_deposit_blocks = saved_blocks;
+    if (st) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail_hip(e, "hipGraphInstantiate");
+    if (c->graphs.size() >= 8) {
+        auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                   [](const GraphEntry &a, const GraphEntry &b) {
+                                       return a.last_use < b.last_use;
+                                   });
+        hipGraphExecDestroy(it->exec);
+        c->graphs.erase(it);
+    }
+    GraphEntry ge;
+    ge.key = std::move(key);
+    ge.exec = exec;
+    ge.last_use = ++c->use_counter;
+    c->graphs.push_back(std::move(ge));
+    *out = exec;
+    return SCPIC_OK;
+}
+
+// Free-space Green's function of lap G = -2 pi delta on node offsets, with
+// the self-cell value replaced by the cell average of -ln r (from the
+// antiderivative F of ln(x^2+y^2): int_0^a int_0^b = F(a, b)).
+double green_offset(int di, int dj, double dx, double dy)
+{
+    if (di == 0 && dj == 0) {
+        const double a = 0.5 * dx, b = 0.5 * dy;
+        const double f = a * b * (std::log(a * a + b * b) - 3.0) + a * a * std::atan(b / a) +
+                         b * b * std::atan(a / b);
+        return -f / (2.0 * a * b);
+    }
+    const double X = di * dx, Y = dj * dy;
+    return -0.5 * std::log(X * X + Y * Y);
+}
+
+}  // namespace
+
+namespace scpic {
+
+// Spectrum of the 2nx x 2ny periodic kernel Gp(X, Y) = G(min(X, mx-X),
+// min(Y, my-Y)).  Gp is even in both offsets, so its DFT is the real cosine
+// sum; it is taken separably (over Y, then X) and divided by mx*my, the
+// normalisation of the unnormalised inverse transforms.  Layout [ny+1][mx].
+void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t)
+{
+    const int mx = 2 * nx, my = 2 * ny;
+    std::vector<double> cxs(mx), cys(my), gp((size_t)mx * my), h((size_t)mx * (ny + 1));
+    for (int t = 0; t < mx; ++t) cxs[t] = std::cos(2.0 * M_PI * t / mx);
+    for (int t = 0; t < my; ++t) cys[t] = std::cos(2.0 * M_PI * t / my);
+    for (int X = 0; X < mx; ++X)
+        for (int Y = 0; Y < my; ++Y)
+            gp[(size_t)X * my + Y] = green_offset(std::min(X, mx - X), std::min(Y, my - Y), dx, dy);
+    for (int X = 0; X < mx; ++X)
+        for (int l = 0; l <= ny; ++l) {
+            double s = 0.0;
+            for (int Y = 0; Y < my; ++Y) s += gp[(size_t)X * my + Y] * cys[((size_t)l * Y) % my];
+            h[(size_t)X * (ny + 1) + l] = s;
+        }
+    const double norm = 1.0 / ((double)mx * (double)my);
+    for (int l = 0; l <= ny; ++l)
+        for (int k = 0; k < mx; ++k) {
+            double s = 0.0;
+            for (int X = 0; X < mx; ++X) s += h[(size_t)X * (ny + 1) + l] * cxs[((size_t)k * X) % mx];
+            ghat_t[(size_t)l * mx + k] = s * norm;
+        }
+}
+
+}  // namespace scpic
+
+namespace {
+
+template <typename T>
+scpic_status upload_tables(scpic_ctx *c)
+{
+    const int nx = c->grid.nx, ny = c->grid.ny, mx = 2 * nx, my = 2 * ny;
+    std::vector<double> ghat((size_t)(ny + 1) * mx);
+    green_spectrum_host(nx, ny, c->grid.dx, c->grid.dy, ghat.data());
+    std::vector<T> g_t(ghat.size()), twx(2 * (size_t)mx), twy(2 * (size_t)my), sx(mx), sy(ny + 1);
+    for (size_t i = 0; i < ghat.size(); ++i) g_t[i] = (T)ghat[i];
+    for (int t = 0; t < mx; ++t) {
+        twx[2 * t] = (T)std::cos(2.0 * M_PI * t / mx);
+        twx[2 * t + 1] = (T)(-std::sin(2.0 * M_PI * t / mx));
+        sx[t] = (T)(std::sin(2.0 * M_PI * t / mx) / c->grid.dx);
+    }
+    for (int t = 0; t < my; ++t) {
+        twy[2 * t] = (T)std::cos(2.0 * M_PI * t / my);
+        twy[2 * t + 1] = (T)(-std::sin(2.0 * M_PI * t / my));
+    }
+    for (int l = 0; l <= ny; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / c->grid.dy);
+    SCPIC_HIP_TRY(hipMemcpy(c->sw.ghat_t, g_t.data(), sizeof(T) * g_t.size(), hipMemcpyHostToDevice), "upload ghat");
+    SCPIC_HIP_TRY(hipMemcpy(c->sw.tw_x, twx.data(), sizeof(T) * twx.size(), hipMemcpyHostToDevice), "upload twiddles");
+    SCPIC_HIP_TRY(hipMemcpy(c->sw.tw_y, twy.data(), sizeof(T) * twy.size(), hipMemcpyHostToDevice), "upload twiddles");
+    SCPIC_HIP_TRY(hipMemcpy(c->sw.sx, sx.data(), sizeof(T) * sx.size(), hipMemcpyHostToDevice), "upload sx");
+    SCPIC_HIP_TRY(hipMemcpy(c->sw.sy, sy.data(), sizeof(T) * sy.size(), hipMemcpyHostToDevice), "upload sy");
+    return SCPIC_OK;
+}
+
+scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision, void *stream)
+{
+    c->grid = *grid;
+    c->mixed = precision == SCPIC_MIXED;
+    c->stream = (hipStream_t)stream;
+    c->geom.nx = grid->nx;
+    c->geom.ny = grid->ny;
+    c->geom.x_min = grid->x_min;
+    c->geom.y_min = grid->y_min;
+    c->geom.inv_dx = 1.0 / grid->dx;
+    c->geom.inv_dy = 1.0 / grid->dy;
+    SCPIC_HIP_TRY(hipGetDevice(&c->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    SCPIC_HIP_TRY(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    c->max_blocks = 2 * c->n_cu;
+    const int nx = grid->nx, ny = grid->ny, ncell = nx * ny;
+    const size_t lds = sizeof(uint32_t) * (size_t)ncell;
+    if (lds + 64 > prop.sharedMemPerBlock)
+        return fail(SCPIC_EUNSUPPORTED, "charge grid does not fit the workgroup's LDS");
+    const size_t fe = field_elem_size(c);
+    const size_t ce = 2 * fe;
+    scpic_status st;
+    void *p;
+#define ALLOC(dst, bytes)                               \
+    do {                                                \
+        if ((st = dev_alloc(c, &p, (bytes)))) return st; \
+        dst = decltype(dst)(p);                         \
+    } while (0)
+    ALLOC(c->dep.partial, sizeof(uint32_t) * (size_t)c->max_blocks * ncell);
+    ALLOC(c->dep.header, sizeof(BlockHeader) * (size_t)c->max_blocks);
+    ALLOC(c->dep.carry, sizeof(unsigned long long) * (size_t)ncell);
+    ALLOC(c->q, sizeof(int64_t) * (size_t)ncell);
+    ALLOC(c->n_in, sizeof(int64_t));
+    c->sw.nx = nx;
+    c->sw.ny = ny;
+    c->sw.mx = 2 * nx;
+    c->sw.my = 2 * ny;
+    c->sw.log2_mx = ilog2(2 * nx);
+    c->sw.log2_my = ilog2(2 * ny);
+    c->sw.mixed = c->mixed;
+    ALLOC(c->sw.tw_x, ce * 2 * nx);
+    ALLOC(c->sw.tw_y, ce * 2 * ny);
+    ALLOC(c->sw.ghat_t, fe * (size_t)(ny + 1) * 2 * nx);
+    ALLOC(c->sw.sx, fe * 2 * nx);
+    ALLOC(c->sw.sy, fe * (ny + 1));
+    ALLOC(c->sw.spec_a, ce * (size_t)(ny + 1) * nx);
+    ALLOC(c->sw.spec_bx, ce * (size_t)(ny + 1) * nx);
+    ALLOC(c->sw.spec_by, ce * (size_t)(ny + 1) * nx);
+    ALLOC(c->ex, fe * ncell);
+    ALLOC(c->ey, fe * ncell);
+#undef ALLOC
+    SCPIC_HIP_TRY(hipMemset(c->dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
+    SCPIC_HIP_TRY(hipMemset(c->dep.header, 0, sizeof(BlockHeader) * c->max_blocks), "hipMemset");
+    SCPIC_HIP_TRY(hipMemset(c->ex, 0, fe * ncell), "hipMemset");
+    SCPIC_HIP_TRY(hipMemset(c->ey, 0, fe * ncell), "hipMemset");
+    st = c->mixed ? upload_tables<float>(c) : upload_tables<double>(c);
+    if (st) return st;
+    SCPIC_HIP_TRY(prepare_pass_kernels(lds), "hipFuncSetAttribute");
+    SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    return SCPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t scpic_version(void) { return 100; }
+
+const char *scpic_last_error(void) { return g_last_error.c_str(); }
+
+scpic_status scpic_create(scpic_ctx **out, const scpic_grid *grid, int32_t precision,
+                          void *hip_stream)
+{
+    g_last_error.clear();
+    if (!out) return fail(SCPIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid) return fail(SCPIC_EINVAL, "grid is NULL");
+    if (precision != SCPIC_FP64 && precision != SCPIC_MIXED)
+        return fail(SCPIC_EINVAL, "precision must be SCPIC_FP64 or SCPIC_MIXED");
+    if (!(grid->dx > 0.0) || !(grid->dy > 0.0) || !std::isfinite(grid->dx) ||
+        !std::isfinite(grid->dy) || !std::isfinite(grid->x_min) || !std::isfinite(grid->y_min))
+        return fail(SCPIC_EINVAL, "grid spacing must be positive and finite, origin finite");
+    if (!is_pow2_in(grid->nx, 8, 256) || !is_pow2_in(grid->ny, 8, 256))
+        return fail(SCPIC_EUNSUPPORTED, "nx and ny must be powers of two in [8, 256]");
+    if ((int64_t)grid->nx * grid->ny > kMaxCells)
+        return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 16384 (LDS charge grid)");
+    scpic_ctx *c = new (std::nothrow) scpic_ctx();
+    if (!c) return fail(SCPIC_ENOMEM, "host allocation failed");
+    scpic_status st = create_impl(c, grid, precision, hip_stream);
+    if (st) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_destroy(scpic_ctx *ctx)
+{
+    g_last_error.clear();
+    if (!ctx) return SCPIC_OK;
+    hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_set_stream(scpic_ctx *ctx, void *hip_stream)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    ctx->stream = (hipStream_t)hip_stream;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    switch (option) {
+    case SCPIC_OPT_USE_GRAPH:
+        ctx->use_graph = value != 0;
+        return SCPIC_OK;
+    case SCPIC_OPT_PASS_BLOCKS:
+        if (value < 0 || value > ctx->max_blocks)
+            return fail(SCPIC_EINVAL, "pass blocks must be in [0, " + std::to_string(ctx->max_blocks) + "]");
+        ctx->pass_blocks = (int)value;
+        return SCPIC_OK;
+    case SCPIC_OPT_PASS_THREADS:
+        if (value != 256 && value != 512 && value != 1024)
+            return fail(SCPIC_EINVAL, "pass threads must be 256, 512 or 1024");
+        ctx->pass_threads = (int)value;
+        return SCPIC_OK;
+    default:
+        return fail(SCPIC_EINVAL, "unknown option " + std::to_string(option));
+    }
+}
+
+scpic_status scpic_push(scpic_ctx *ctx, const scpic_particles *parts,
+                        const scpic_element *elements, int32_t n_el)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    std::vector<const scpic_element *> els;
+    if (scpic_status st = collect_elements(elements, n_el, els, false)) return st;
+    if (els.empty() || parts->n == 0) return SCPIC_OK;
+    std::vector<PassOp> ops;
+    emit_segment(ops, false, 0.0, els, false);
+    for (const PassOp &op : ops)
+        if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, nullptr, nullptr)) return st;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_deposit(scpic_ctx *ctx, const scpic_particles *parts, int64_t *rho,
+                           int64_t *n_in)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (!rho) return fail(SCPIC_EINVAL, "rho is NULL");
+    PassOp op;
+    std::memset(&op, 0, sizeof(op));
+    op.deposit = true;
+    if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, nullptr, nullptr)) return st;
+    const int blocks = parts->n > 0 ? ctx->last_deposit_blocks : 0;
+    hipError_t e = launch_reduce(ctx->stream, ctx->dep, blocks, ctx->grid.nx, ctx->grid.ny, rho, n_in);
+    if (e != hipSuccess) return fail_hip(e, "reduce launch");
+    return SCPIC_OK;
+}
+
+scpic_status scpic_solve(scpic_ctx *ctx, const int64_t *rho, double scale, void *ex, void *ey)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (!rho || !ex || !ey) return fail(SCPIC_EINVAL, "rho, ex and ey must be non-NULL");
+    if (!std::isfinite(scale)) return fail(SCPIC_EINVAL, "scale must be finite");
+    hipError_t e = launch_solve(ctx->stream, ctx->sw, rho, scale, ex, ey);
+    if (e != hipSuccess) return fail_hip(e, "solve launch");
+    return SCPIC_OK;
+}
+
+scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void *ex,
+                        const void *ey, double kappa)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (!ex || !ey) return fail(SCPIC_EINVAL, "ex and ey must be non-NULL");
+    if (!std::isfinite(kappa)) return fail(SCPIC_EINVAL, "kappa must be finite");
+    PassOp op;
+    std::memset(&op, 0, sizeof(op));
+    op.kick = true;
+    op.kappa = kappa;
+    return enqueue_pass(ctx, ctx->stream, parts, op, ex, ey);
+}
+
+scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t kick, double kappa,
+                        const scpic_element *elements, int32_t n_el, int32_t deposit)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (n_el > kMaxPassElements) return fail(SCPIC_EINVAL, "at most 12 elements per pass");
+    std::vector<const scpic_element *> els;
+    if (scpic_status st = collect_elements(elements, n_el, els, true)) return st;
+    for (auto *e : els)
+        if (e->kind == SCPIC_EL_SC) return fail(SCPIC_EINVAL, "a pass takes no SC element");
+    PassOp op;
+    op.kick = kick != 0;
+    op.kappa = kappa;
+    op.els = pack(els, 0, els.size());
+    op.deposit = deposit != 0;
+    return enqueue_pass(ctx, ctx->stream, parts, op, ctx->ex, ctx->ey);
+}
+
+scpic_status scpic_reduce_solve(scpic_ctx *ctx, double scale)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    return enqueue_grid_phase(ctx, ctx->stream, scale);
+}
+
+scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (!ex || !ey) return fail(SCPIC_EINVAL, "ex and ey must be non-NULL");
+    const size_t bytes = field_elem_size(ctx) * (size_t)ctx->grid.nx * ctx->grid.ny;
+    SCPIC_HIP_TRY(hipMemcpyAsync(ex, ctx->ex, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy ex");
+    SCPIC_HIP_TRY(hipMemcpyAsync(ey, ctx->ey, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy ey");
+    return SCPIC_OK;
+}
+
+scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scpic_element *turn,
+                         int32_t n_el, int32_t n_turns)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (n_turns < 0) return fail(SCPIC_EINVAL, "n_turns is negative");
+    std::vector<const scpic_element *> all;
+    if (scpic_status st = collect_elements(turn, n_el, all, true)) return st;
+    if (n_turns == 0 || all.empty() || parts->n == 0) return SCPIC_OK;
+    const double scale = 1.0 / (kChargeOne * (double)parts->n);
+
+    std::vector<PassOp> first, steady;
+    std::vector<const scpic_element *> trailing;
+    bool any_sc = false;
+    double last_kappa = 0.0;
+    build_turn(all, true, first, any_sc, last_kappa, trailing);
+    if (!any_sc) {
+        for (int t = 0; t < n_turns; ++t)
+            if (scpic_status st = enqueue_ops(ctx, ctx->stream, parts, first, scale)) return st;
+        return SCPIC_OK;
+    }
+    build_turn(all, false, steady, any_sc, last_kappa, trailing);
+    if (scpic_status st = enqueue_ops(ctx, ctx->stream, parts, first, scale)) return st;
+    if (n_turns > 1) {
+        if (ctx->use_graph) {
+            hipGraphExec_t exec = nullptr;
+            if (scpic_status st = get_turn_graph(ctx, parts, steady, scale, &exec)) return st;
+            for (int t = 1; t < n_turns; ++t)
+                SCPIC_HIP_TRY(hipGraphLaunch(exec, ctx->stream), "hipGraphLaunch");
+            // the graph's last depositing pass used the same block count
+            for (const PassOp &op : steady)
+                if (op.deposit) ctx->last_deposit_blocks = blocks_for(ctx, parts->n, true);
+        } else {
+            for (int t = 1; t < n_turns; ++t)
+                if (scpic_status st = enqueue_ops(ctx, ctx->stream, parts, steady, scale)) return st;
+        }
+    }
+    // epilogue: the last location's kick, then the elements after it
+    std::vector<PassOp> tail;
+    emit_segment(tail, true, last_kappa, trailing, false);
+    return enqueue_ops(ctx, ctx->stream, parts, tail, scale);
+}
+
+}  // extern "C"

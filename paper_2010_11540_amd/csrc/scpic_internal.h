@@ -1,0 +1,91 @@
+// Internal declarations shared by the host-side translation units of libscpic.
+// Not installed; the public interface is include/scpic.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "scpic.h"
+
+namespace scpic {
+
+// Fixed-point charge: 12 fractional bits per axis, 2^24 units per particle.
+constexpr int kFracBits = 12;
+constexpr int kFracOne = 1 << kFracBits;  // 4096
+constexpr double kChargeOne = 16777216.0;  // 2^24
+
+// Elements a single particle pass can carry in its kernel arguments.
+constexpr int kMaxPassElements = 12;
+
+// Largest FFT length (2 * largest grid side) and grid cells held in LDS.
+constexpr int kMaxFft = 512;
+constexpr int kMaxCells = 16384;
+
+// Per-block header written by a depositing pass: bounding box of the cells it
+// touched (inclusive; empty when i0 > i1) and how many particles it deposited.
+struct BlockHeader {
+    int32_t i0, i1, j0, j1;
+    int32_t count;
+    int32_t pad[3];
+};
+
+// Grid geometry as the kernels see it.  inv_dx / inv_dy are 1.0/dx and
+// 1.0/dy computed once on the host in FP64.
+struct GridGeom {
+    int32_t nx, ny;
+    double x_min, y_min, inv_dx, inv_dy;
+};
+
+// Elements of one pass, passed by value in the kernel arguments (read with
+// scalar loads, uniform across the wave).
+struct PassElements {
+    int32_t n_el;
+    int32_t kind[kMaxPassElements];
+    double p[kMaxPassElements][16];
+};
+
+// Device-side buffers of the charge partials.
+struct DepositTarget {
+    uint32_t *partial;            // [blocks][nx*ny] bounding-box-packed cells
+    BlockHeader *header;          // [blocks]
+    unsigned long long *carry;    // [nx*ny] whole 2^32 overflows of LDS cells
+};
+
+struct ParticlePtrs {
+    double *x, *px, *y, *py;
+    uint8_t *lost;
+    int64_t n;
+};
+
+// ---- launchers (particles.hip) ------------------------------------------
+hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
+                       bool mixed, const void *ex, const void *ey, double kappa,
+                       const PassElements &els, bool deposit, const DepositTarget &dep,
+                       int blocks, int threads);
+
+hipError_t prepare_pass_kernels(size_t lds_bytes);
+
+hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,
+                         int64_t *q, int64_t *n_in);
+
+// ---- launchers (fft_solve.hip) -------------------------------------------
+struct SolveWorkspace {
+    int nx, ny, mx, my, log2_mx, log2_my;
+    bool mixed;
+    void *tw_x, *tw_y;   // [mx], [my] complex twiddles exp(-2 pi i t / m)
+    void *ghat_t;        // [ny+1][mx] real Green's spectrum / (mx my), transposed
+    void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [ny+1] sin(2 pi l / my)/dy
+    void *spec_a;        // [ny+1][nx] complex, rows transformed
+    void *spec_bx, *spec_by;  // [nx][ny+1] complex, after the column pass
+};
+
+hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
+                        void *ex, void *ey);
+
+// Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
+// the padded 2nx x 2ny periodic kernel.
+void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t);
+
+}  // namespace scpic

@@ -20,3 +20,16 @@ def orc():
     if not (ROOT / "oracle" / "liborc.so").exists():
         oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP binding, on a machine with a GPU.  A missing library on a GPU
+    machine is an error, not a skip."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    from paper_2010_11540_amd import scpic
+    scpic.load_library()
+    torch.cuda.init()
+    return scpic
