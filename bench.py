@@ -49,7 +49,23 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=6.0,
                     help="wall-clock budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 64 MiB device-to-device copy 20 times (the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 64 * 1024 * 1024 // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(20):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 8, "bytes_written": n * 8,
+                                           "launches": 20}}), flush=True)
 
 
 def source_digest() -> str:
@@ -108,7 +124,6 @@ def main():
               "the space-charge loop is not sharded across GPUs in this build.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2010_11540_amd import inputs, scpic
@@ -117,6 +132,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     w = inputs.workload(args.workload)
     lat = w["lattice"]
     steps_per_turn = int((lat["kind"] == inputs.SC).sum())

@@ -108,9 +108,11 @@ __global__ void __launch_bounds__(kFftThreads)
                const cx<T> *__restrict__ tw, cx<T> *__restrict__ at)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *a = twl + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
+    for (int t = tid; t < my; t += kFftThreads) twl[t] = tw[t];
     const int i0 = 2 * blockIdx.x;
     const int64_t *r0 = q + (size_t)i0 * ny;
     const int64_t *r1 = r0 + ny;
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(kFftThreads)
         }
         a[j] = z;
     }
-    const cx<T> *r = fft_lds(a, b, my, log2my, tw, tid, kFftThreads);
+    const cx<T> *r = fft_lds(a, b, my, log2my, twl, tid, kFftThreads);
     for (int l = tid; l <= ny; l += kFftThreads) {
         const cx<T> zl = r[l];
         const cx<T> zm = conj(r[(my - l) & (my - 1)]);
@@ -141,32 +143,41 @@ __global__ void __launch_bounds__(kFftThreads)
            const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *a = twl + mx;
     cx<T> *b = a + mx;
     cx<T> *c = b + mx;
+    T *gl = reinterpret_cast<T *>(c + mx);
+    T *sxl = gl + mx;
     const int tid = threadIdx.x;
     const int l = blockIdx.x;
     const cx<T> *col = at + (size_t)l * nx;
-    for (int i = tid; i < mx; i += kFftThreads) a[i] = i < nx ? col[i] : cx<T>{T(0), T(0)};
-    cx<T> *r = fft_lds(a, b, mx, log2mx, tw, tid, kFftThreads);
     const T *g = ghat_t + (size_t)l * mx;
+    // stage every input of the column in LDS up front (one round of loads)
+    for (int i = tid; i < mx; i += kFftThreads) {
+        twl[i] = tw[i];
+        gl[i] = g[i];
+        sxl[i] = sx[i];
+        a[i] = i < nx ? col[i] : cx<T>{T(0), T(0)};
+    }
+    const T syl = sy[l];
+    cx<T> *r = fft_lds(a, b, mx, log2mx, twl, tid, kFftThreads);
     // Inverse transforms as conj(FFT(conj(.))): stage the conjugated inputs.
     for (int k = tid; k < mx; k += kFftThreads) {
-        const T gk = g[k];
+        const T gk = gl[k];
         const cx<T> phi = {r[k].re * gk, r[k].im * gk};
         c[k] = conj(phi);
-        const cx<T> dx = mul_neg_i(cx<T>{phi.re * sx[k], phi.im * sx[k]});
+        const cx<T> dx = mul_neg_i(cx<T>{phi.re * sxl[k], phi.im * sxl[k]});
         r[k] = conj(dx);
     }
     cx<T> *o = (r == a) ? b : a;
-    const cx<T> *rx = fft_lds(r, o, mx, log2mx, tw, tid, kFftThreads);
+    const cx<T> *rx = fft_lds(r, o, mx, log2mx, twl, tid, kFftThreads);
     for (int i = tid; i < nx; i += kFftThreads) bx[(size_t)i * (ny + 1) + l] = conj(rx[i]);
     // rx may alias r or o; c is untouched.  Use the two free buffers for the
     // second inverse transform.
     cx<T> *f0 = c;
     cx<T> *f1 = (rx == a) ? b : a;
-    const cx<T> *ry = fft_lds(f0, f1, mx, log2mx, tw, tid, kFftThreads);
-    const T syl = sy[l];
+    const cx<T> *ry = fft_lds(f0, f1, mx, log2mx, twl, tid, kFftThreads);
     for (int i = tid; i < nx; i += kFftThreads) {
         const cx<T> p = conj(ry[i]);
         by[(size_t)i * (ny + 1) + l] = mul_neg_i(cx<T>{p.re * syl, p.im * syl});
@@ -174,17 +185,21 @@ __global__ void __launch_bounds__(kFftThreads)
 }
 
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
-// i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.
-template <typename T, typename TO>
+// i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
+// either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
+template <typename T>
 __global__ void __launch_bounds__(kFftThreads)
     k_rows_inv(const cx<T> *__restrict__ bx, const cx<T> *__restrict__ by, int nx, int ny, int my,
-               int log2my, const cx<T> *__restrict__ tw, TO *__restrict__ ex, TO *__restrict__ ey)
+               int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
+               cx<T> *__restrict__ ef)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *a = twl + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
     const int i = blockIdx.x;
+    for (int t = tid; t < my; t += kFftThreads) twl[t] = tw[t];
     const cx<T> *rx = bx + (size_t)i * (ny + 1);
     const cx<T> *ry = by + (size_t)i * (ny + 1);
     for (int l = tid; l <= ny; l += kFftThreads) {
@@ -193,20 +208,24 @@ __global__ void __launch_bounds__(kFftThreads)
         a[l] = conj(X + mul_pos_i(Y));
         if (l > 0 && l < ny) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
     }
-    const cx<T> *r = fft_lds(a, b, my, log2my, tw, tid, kFftThreads);
-    for (int j = tid; j < ny; j += kFftThreads) {
-        const cx<T> z = conj(r[j]);
-        ex[(size_t)i * ny + j] = (TO)z.re;
-        ey[(size_t)i * ny + j] = (TO)z.im;
+    const cx<T> *r = fft_lds(a, b, my, log2my, twl, tid, kFftThreads);
+    if (ef) {
+        for (int j = tid; j < ny; j += kFftThreads) ef[(size_t)i * ny + j] = conj(r[j]);
+    } else {
+        for (int j = tid; j < ny; j += kFftThreads) {
+            const cx<T> z = conj(r[j]);
+            ex[(size_t)i * ny + j] = z.re;
+            ey[(size_t)i * ny + j] = z.im;
+        }
     }
 }
 
 template <typename T>
 hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
-                          void *ex, void *ey)
+                          void *ex, void *ey, void *ef)
 {
-    const size_t row_lds = 2 * sizeof(cx<T>) * (size_t)w.my;
-    const size_t col_lds = 3 * sizeof(cx<T>) * (size_t)w.mx;
+    const size_t row_lds = 3 * sizeof(cx<T>) * (size_t)w.my;
+    const size_t col_lds = (4 * sizeof(cx<T>) + 2 * sizeof(T)) * (size_t)w.mx;
     hipLaunchKernelGGL(k_rows_fwd<T>, dim3(w.nx / 2), dim3(kFftThreads), row_lds, s, q, scale,
                        w.nx, w.ny, w.my, w.log2_my, (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a);
     hipError_t e = hipGetLastError();
@@ -217,19 +236,19 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const int64_t 
                        (cx<T> *)w.spec_by);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_rows_inv<T, T>), dim3(w.nx), dim3(kFftThreads), row_lds, s,
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kFftThreads), row_lds, s,
                        (const cx<T> *)w.spec_bx, (const cx<T> *)w.spec_by, w.nx, w.ny, w.my,
-                       w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey);
+                       w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
-                        void *ex, void *ey)
+                        void *ex, void *ey, void *ef)
 {
-    return w.mixed ? launch_solve_t<float>(s, w, q, scale, ex, ey)
-                   : launch_solve_t<double>(s, w, q, scale, ex, ey);
+    return w.mixed ? launch_solve_t<float>(s, w, q, scale, ex, ey, ef)
+                   : launch_solve_t<double>(s, w, q, scale, ex, ey, ef);
 }
 
 }  // namespace scpic

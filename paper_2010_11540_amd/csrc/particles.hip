@@ -45,14 +45,31 @@ __device__ __forceinline__ bool cic(const GridGeom &g, double x, double y, Cic &
     return true;
 }
 
-// Interpolated field at the particle: weights / 2^24 applied to the four
-// nodes, summed in node order (i,j), (i+1,j), (i,j+1), (i+1,j+1).
+// Interpolated field at the particle from the interleaved node field
+// (e[2c] = Ex, e[2c+1] = Ey, one 2-vector load per node): weights / 2^24
+// applied to the four nodes, summed in node order (i,j), (i+1,j), (i,j+1),
+// (i+1,j+1).
 template <typename TE>
-__device__ __forceinline__ TE gather(const TE *__restrict__ e, int c00, int ny, const Cic &c)
+struct Vec2;
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+
+template <typename TE>
+__device__ __forceinline__ void gather(const TE *__restrict__ e, int c00, int ny, const Cic &c,
+                                       TE &fx, TE &fy)
 {
-    const TE s = (TE)c.w00 * e[c00] + (TE)c.w10 * e[c00 + ny] + (TE)c.w01 * e[c00 + 1] +
-                 (TE)c.w11 * e[c00 + ny + 1];
-    return s * (TE)(1.0 / kChargeOne);
+    using V = typename Vec2<TE>::type;
+    const V *ev = reinterpret_cast<const V *>(e);
+    const V e00 = ev[c00], e10 = ev[c00 + ny], e01 = ev[c00 + 1], e11 = ev[c00 + ny + 1];
+    const TE w00 = (TE)c.w00, w10 = (TE)c.w10, w01 = (TE)c.w01, w11 = (TE)c.w11;
+    fx = (w00 * e00.x + w10 * e10.x + w01 * e01.x + w11 * e11.x) * (TE)(1.0 / kChargeOne);
+    fy = (w00 * e00.y + w10 * e10.y + w01 * e01.y + w11 * e11.y) * (TE)(1.0 / kChargeOne);
 }
 
 // One element applied to one particle (Sec. III): v <- M v for the linear
@@ -79,17 +96,23 @@ __device__ __forceinline__ void apply_element(int kind, const double *__restrict
     }
 }
 
-// Add w charge units to an LDS cell.  The 32-bit cell wraps after 2^32 units
-// (256 particles sitting exactly on one node); the returned old value shows a
-// wrap, and the lost 2^32 goes to the global carry grid, which the reduction
-// adds back.  Wraps need that many particles of one workgroup on one node, so
-// the global atomic is rare.
-__device__ __forceinline__ void lds_add(uint32_t *q, int c, uint32_t w,
-                                        unsigned long long *__restrict__ carry)
+// Add a particle's four weights to the LDS charge grid.  A 32-bit cell wraps
+// after 2^32 units (256 particles sitting exactly on one node); the returned
+// old value shows a wrap, and the lost 2^32 goes to the global carry grid,
+// which the reduction adds back.  All four atomics are issued before any
+// return value is inspected.  Wraps need that many particles of one
+// workgroup on one node, so the global atomic is rare.
+__device__ __forceinline__ void lds_deposit(uint32_t *q, int c00, int ny, const Cic &c,
+                                            unsigned long long *__restrict__ carry)
 {
-    if (w == 0) return;
-    const uint32_t old = atomicAdd(&q[c], w);
-    if (old + w < old) atomicAdd(&carry[c], 1ull << 32);
+    const uint32_t o00 = atomicAdd(&q[c00], c.w00);
+    const uint32_t o10 = atomicAdd(&q[c00 + ny], c.w10);
+    const uint32_t o01 = atomicAdd(&q[c00 + 1], c.w01);
+    const uint32_t o11 = atomicAdd(&q[c00 + ny + 1], c.w11);
+    if (o00 + c.w00 < o00) atomicAdd(&carry[c00], 1ull << 32);
+    if (o10 + c.w10 < o10) atomicAdd(&carry[c00 + ny], 1ull << 32);
+    if (o01 + c.w01 < o01) atomicAdd(&carry[c00 + 1], 1ull << 32);
+    if (o11 + c.w11 < o11) atomicAdd(&carry[c00 + ny + 1], 1ull << 32);
 }
 
 __device__ __forceinline__ int wave_min(int v)
@@ -111,9 +134,11 @@ __device__ __forceinline__ int wave_sum(int v)
     return v;
 }
 
-// The fused particle pass.  Each thread walks particles p = tid, tid + T, ...
-// (T = all threads of the launch; consecutive lanes take consecutive
-// particles, so every SoA load and store is coalesced):
+// The fused particle pass.  Thread t of the launch (T threads in all) takes
+// the particles t + u*T + k*U*T, u < U: consecutive lanes take consecutive
+// particles, so every SoA load and store is coalesced, and each thread issues
+// the loads of its U particles before using any, so U particles per lane are
+// in flight at once.  For each particle:
 //   KICK     gather the node field at the particle with the deposit weights
 //            and kick px, py by kappa * E (a particle found outside the domain
 //            is marked lost and frozen);
@@ -122,17 +147,18 @@ __device__ __forceinline__ int wave_sum(int v)
 //            of the charge grid in LDS (particles outside are marked lost).
 // At the end each workgroup writes the bounding box of the cells it touched,
 // packed densely, to its own slice of the partials (no global atomics).
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, int U>
 __global__ void __launch_bounds__(1024)
-    k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ex, const TE *__restrict__ ey,
-           double kappa, PassElements els, DepositTarget dep)
+    k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
+           PassElements els, DepositTarget dep)
 {
     extern __shared__ uint32_t lds_q[];
     __shared__ int s_box[4];
     __shared__ int s_count;
     const int ncell = g.nx * g.ny;
     if constexpr (DEPOSIT) {
-        for (int c = threadIdx.x; c < ncell; c += blockDim.x) lds_q[c] = 0u;
+        uint4 *q4 = reinterpret_cast<uint4 *>(lds_q);
+        for (int c = threadIdx.x; c < ncell / 4; c += blockDim.x) q4[c] = make_uint4(0, 0, 0, 0);
         if (threadIdx.x == 0) {
             s_box[0] = INT_MAX;
             s_box[1] = -1;
@@ -144,46 +170,77 @@ __global__ void __launch_bounds__(1024)
     }
     const bool moves = KICK || els.n_el > 0;
     int bi0 = INT_MAX, bi1 = -1, bj0 = INT_MAX, bj1 = -1, cnt = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
-        if (P.lost && P.lost[p]) continue;
-        double x = P.x[p], px = P.px[p], y = P.y[p], py = P.py[p];
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; base < P.n;
+         base += U * T) {
+        double x[U], px[U], y[U], py[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = base + u * T;
+            act[u] = p < P.n;
+            uint8_t lf = 0;
+            if (act[u]) {
+                x[u] = P.x[p];
+                px[u] = P.px[p];
+                y[u] = P.y[p];
+                py[u] = P.py[p];
+                if (P.lost) lf = P.lost[p];
+            }
+            act[u] = act[u] && lf == 0;
+        }
         if constexpr (KICK) {
-            Cic c;
-            if (cic(g, x, y, c)) {
-                const int c00 = c.i * g.ny + c.j;
-                const TE fx = gather(ex, c00, g.ny, c);
-                const TE fy = gather(ey, c00, g.ny, c);
-                px = px + kappa * (double)fx;
-                py = py + kappa * (double)fy;
-            } else if (P.lost) {
-                P.lost[p] = 1;
-                continue;
+            Cic c[U];
+            bool in[U];
+            TE fx[U], fy[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) in[u] = act[u] && cic(g, x[u], y[u], c[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (in[u]) gather(ef, c[u].i * g.ny + c[u].j, g.ny, c[u], fx[u], fy[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (in[u]) {
+                    px[u] = px[u] + kappa * (double)fx[u];
+                    py[u] = py[u] + kappa * (double)fy[u];
+                } else if (act[u] && P.lost) {
+                    P.lost[base + u * T] = 1;
+                    act[u] = false;
+                }
             }
         }
-        for (int e = 0; e < els.n_el; ++e) apply_element(els.kind[e], els.p[e], x, px, y, py);
+        for (int e = 0; e < els.n_el; ++e) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) apply_element(els.kind[e], els.p[e], x[u], px[u], y[u], py[u]);
+        }
         if constexpr (DEPOSIT) {
-            Cic c;
-            if (cic(g, x, y, c)) {
-                const int c00 = c.i * g.ny + c.j;
-                lds_add(lds_q, c00, c.w00, dep.carry);
-                lds_add(lds_q, c00 + g.ny, c.w10, dep.carry);
-                lds_add(lds_q, c00 + 1, c.w01, dep.carry);
-                lds_add(lds_q, c00 + g.ny + 1, c.w11, dep.carry);
-                bi0 = min(bi0, c.i);
-                bi1 = max(bi1, c.i + 1);
-                bj0 = min(bj0, c.j);
-                bj1 = max(bj1, c.j + 1);
-                ++cnt;
-            } else if (P.lost) {
-                P.lost[p] = 1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!act[u]) continue;
+                Cic c;
+                if (cic(g, x[u], y[u], c)) {
+                    lds_deposit(lds_q, c.i * g.ny + c.j, g.ny, c, dep.carry);
+                    bi0 = min(bi0, c.i);
+                    bi1 = max(bi1, c.i + 1);
+                    bj0 = min(bj0, c.j);
+                    bj1 = max(bj1, c.j + 1);
+                    ++cnt;
+                } else if (P.lost) {
+                    P.lost[base + u * T] = 1;
+                }
             }
         }
         if (moves) {
-            P.x[p] = x;
-            P.px[p] = px;
-            P.y[p] = y;
-            P.py[p] = py;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!act[u]) continue;
+                const int64_t p = base + u * T;
+                P.x[p] = x[u];
+                P.px[p] = px[u];
+                P.y[p] = y[u];
+                P.py[p] = py[u];
+            }
         }
     }
     if constexpr (DEPOSIT) {
@@ -224,25 +281,29 @@ __global__ void __launch_bounds__(1024)
 }
 
 // Exact charge grid q = sum over workgroups of their partials (+ carries).
-// A workgroup owns 64 consecutive cells (one per lane); its 16 waves split the
-// partials, so 16 independent loads per lane are in flight, and the per-wave
-// sums are combined in LDS.  The carry grid is consumed and cleared here.
+// The block headers are staged in LDS first; then a workgroup owns 64
+// consecutive cells (one per lane) and its 16 waves split the partials, so
+// every partial load of a lane is independent and in flight together; the
+// per-wave sums are combined in LDS.  The carry grid is consumed and cleared.
 constexpr int kReduceWaves = 16;
 
 __global__ void __launch_bounds__(kReduceWaves * 64)
     k_reduce(DepositTarget dep, int nblocks, int nx, int ny, int64_t *__restrict__ q,
              int64_t *__restrict__ n_in)
 {
+    __shared__ BlockHeader hdr[kMaxPassBlocks];
     __shared__ unsigned long long part[kReduceWaves][64];
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) hdr[b] = dep.header[b];
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ncell = nx * ny;
     const int c = blockIdx.x * 64 + lane;
     const int i = c / ny, j = c - i * ny;
     unsigned long long s = 0;
-#pragma unroll 4
+#pragma unroll 8
     for (int b = wave; b < nblocks; b += kReduceWaves) {
-        const BlockHeader h = dep.header[b];
+        const BlockHeader h = hdr[b];
         if (i >= h.i0 && i <= h.i1 && j >= h.j0 && j <= h.j1) {
             const int w = h.j1 - h.j0 + 1;
             s += dep.partial[(size_t)b * ncell + (i - h.i0) * w + (j - h.j0)];
@@ -260,21 +321,41 @@ __global__ void __launch_bounds__(kReduceWaves * 64)
     }
     if (n_in != nullptr && blockIdx.x == 0 && wave == 1) {
         long long cnt = 0;
-        for (int b = lane; b < nblocks; b += 64) cnt += dep.header[b].count;
+        for (int b = lane; b < nblocks; b += 64) cnt += hdr[b].count;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
         if (lane == 0) *n_in = cnt;
     }
 }
 
+// Between two node arrays (ex, ey) and the internal interleaved layout ef
+// (Ex, Ey per node), in either direction.
+template <typename TE, bool TO_INTERLEAVED>
+__global__ void __launch_bounds__(256)
+    k_interleave(TE *__restrict__ ex, TE *__restrict__ ey, TE *__restrict__ ef, int ncell)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) {
+        if (TO_INTERLEAVED) {
+            ef[2 * c] = ex[c];
+            ef[2 * c + 1] = ey[c];
+        } else {
+            ex[c] = ef[2 * c];
+            ey[c] = ef[2 * c + 1];
+        }
+    }
+}
+
+constexpr int kUnroll = 4;
+
 template <typename TE, bool KICK, bool DEPOSIT>
-hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, const void *ex,
-                         const void *ey, double kappa, const PassElements &els,
-                         const DepositTarget &dep, int blocks, int threads)
+hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, const void *ef,
+                         double kappa, const PassElements &els, const DepositTarget &dep,
+                         int blocks, int threads)
 {
     const size_t lds = DEPOSIT ? sizeof(uint32_t) * (size_t)g.nx * g.ny : 0;
-    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), lds, s, p, g, (const TE *)ex,
-                       (const TE *)ey, kappa, els, dep);
+    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT, kUnroll>), dim3(blocks), dim3(threads), lds, s,
+                       p, g, (const TE *)ef, kappa, els, dep);
     return hipGetLastError();
 }
 
@@ -285,10 +366,10 @@ hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g
 // stream capture.
 hipError_t prepare_pass_kernels(size_t lds_bytes)
 {
-    const void *kerns[] = {(const void *)k_pass<double, true, true>,
-                           (const void *)k_pass<double, false, true>,
-                           (const void *)k_pass<float, true, true>,
-                           (const void *)k_pass<float, false, true>};
+    const void *kerns[] = {(const void *)k_pass<double, true, true, kUnroll>,
+                           (const void *)k_pass<double, false, true, kUnroll>,
+                           (const void *)k_pass<float, true, true, kUnroll>,
+                           (const void *)k_pass<float, false, true, kUnroll>};
     for (const void *k : kerns) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
@@ -298,23 +379,44 @@ hipError_t prepare_pass_kernels(size_t lds_bytes)
 }
 
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
-                       bool mixed, const void *ex, const void *ey, double kappa,
-                       const PassElements &els, bool deposit, const DepositTarget &dep,
-                       int blocks, int threads)
+                       bool mixed, const void *ef, double kappa, const PassElements &els,
+                       bool deposit, const DepositTarget &dep, int blocks, int threads)
 {
     if (blocks <= 0) return hipSuccess;
     if (mixed) {
         if (kick)
-            return deposit ? launch_pass_t<float, true, true>(s, p, g, ex, ey, kappa, els, dep, blocks, threads)
-                           : launch_pass_t<float, true, false>(s, p, g, ex, ey, kappa, els, dep, blocks, threads);
-        return deposit ? launch_pass_t<float, false, true>(s, p, g, ex, ey, kappa, els, dep, blocks, threads)
-                       : launch_pass_t<float, false, false>(s, p, g, ex, ey, kappa, els, dep, blocks, threads);
+            return deposit ? launch_pass_t<float, true, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
+                           : launch_pass_t<float, true, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
+        return deposit ? launch_pass_t<float, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
+                       : launch_pass_t<float, false, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
     }
     if (kick)
-        return deposit ? launch_pass_t<double, true, true>(s, p, g, ex, ey, kappa, els, dep, blocks, threads)
-                       : launch_pass_t<double, true, false>(s, p, g, ex, ey, kappa, els, dep, blocks, threads);
-    return deposit ? launch_pass_t<double, false, true>(s, p, g, ex, ey, kappa, els, dep, blocks, threads)
-                   : launch_pass_t<double, false, false>(s, p, g, ex, ey, kappa, els, dep, blocks, threads);
+        return deposit ? launch_pass_t<double, true, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
+                       : launch_pass_t<double, true, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
+    return deposit ? launch_pass_t<double, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
+                   : launch_pass_t<double, false, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
+}
+
+hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
+                             void *ef, int ncell)
+{
+    const dim3 grid((ncell + 255) / 256);
+    if (mixed) {
+        if (to_interleaved)
+            hipLaunchKernelGGL((k_interleave<float, true>), grid, dim3(256), 0, s, (float *)ex,
+                               (float *)ey, (float *)ef, ncell);
+        else
+            hipLaunchKernelGGL((k_interleave<float, false>), grid, dim3(256), 0, s, (float *)ex,
+                               (float *)ey, (float *)ef, ncell);
+    } else {
+        if (to_interleaved)
+            hipLaunchKernelGGL((k_interleave<double, true>), grid, dim3(256), 0, s, (double *)ex,
+                               (double *)ey, (double *)ef, ncell);
+        else
+            hipLaunchKernelGGL((k_interleave<double, false>), grid, dim3(256), 0, s, (double *)ex,
+                               (double *)ey, (double *)ef, ncell);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,

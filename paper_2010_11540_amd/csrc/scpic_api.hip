@@ -80,7 +80,7 @@ struct scpic_ctx {
     int64_t *q = nullptr;
     int64_t *n_in = nullptr;
     SolveWorkspace sw{};
-    void *ex = nullptr, *ey = nullptr;
+    void *ef = nullptr;  // internal field, interleaved (Ex, Ey) per node
 
     std::vector<void *> allocations;
     std::vector<GraphEntry> graphs;
@@ -201,10 +201,10 @@ void emit_segment(std::vector<PassOp> &ops, bool kick, double kappa,
 }
 
 scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
-                          const PassOp &op, const void *ex, const void *ey)
+                          const PassOp &op)
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
-    hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, ex, ey, op.kappa,
+    hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
                                op.els, op.deposit, c->dep, blocks, c->pass_threads);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
     if (op.deposit) c->last_deposit_blocks = blocks;
@@ -216,7 +216,7 @@ scpic_status enqueue_grid_phase(scpic_ctx *c, hipStream_t s, double scale)
     hipError_t e = launch_reduce(s, c->dep, c->last_deposit_blocks, c->grid.nx, c->grid.ny, c->q,
                                  nullptr);
     if (e != hipSuccess) return fail_hip(e, "reduce launch");
-    e = launch_solve(s, c->sw, c->q, scale, c->ex, c->ey);
+    e = launch_solve(s, c->sw, c->q, scale, nullptr, nullptr, c->ef);
     if (e != hipSuccess) return fail_hip(e, "solve launch");
     return SCPIC_OK;
 }
@@ -256,7 +256,7 @@ scpic_status enqueue_ops(scpic_ctx *c, hipStream_t s, const scpic_particles *par
                          const std::vector<PassOp> &ops, double scale)
 {
     for (const PassOp &op : ops) {
-        scpic_status st = enqueue_pass(c, s, parts, op, c->ex, c->ey);
+        scpic_status st = enqueue_pass(c, s, parts, op);
         if (st) return st;
         if (op.deposit) {
             st = enqueue_grid_phase(c, s, scale);
@@ -425,7 +425,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     hipDeviceProp_t prop;
     SCPIC_HIP_TRY(hipGetDeviceProperties(&prop, c->device), "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
-    c->max_blocks = 2 * c->n_cu;
+    c->max_blocks = std::min(2 * c->n_cu, kMaxPassBlocks);
     const int nx = grid->nx, ny = grid->ny, ncell = nx * ny;
     const size_t lds = sizeof(uint32_t) * (size_t)ncell;
     if (lds + 64 > prop.sharedMemPerBlock)
@@ -459,13 +459,11 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     ALLOC(c->sw.spec_a, ce * (size_t)(ny + 1) * nx);
     ALLOC(c->sw.spec_bx, ce * (size_t)(ny + 1) * nx);
     ALLOC(c->sw.spec_by, ce * (size_t)(ny + 1) * nx);
-    ALLOC(c->ex, fe * ncell);
-    ALLOC(c->ey, fe * ncell);
+    ALLOC(c->ef, 2 * fe * ncell);
 #undef ALLOC
     SCPIC_HIP_TRY(hipMemset(c->dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
     SCPIC_HIP_TRY(hipMemset(c->dep.header, 0, sizeof(BlockHeader) * c->max_blocks), "hipMemset");
-    SCPIC_HIP_TRY(hipMemset(c->ex, 0, fe * ncell), "hipMemset");
-    SCPIC_HIP_TRY(hipMemset(c->ey, 0, fe * ncell), "hipMemset");
+    SCPIC_HIP_TRY(hipMemset(c->ef, 0, 2 * fe * ncell), "hipMemset");
     st = c->mixed ? upload_tables<float>(c) : upload_tables<double>(c);
     if (st) return st;
     SCPIC_HIP_TRY(prepare_pass_kernels(lds), "hipFuncSetAttribute");
@@ -562,7 +560,7 @@ scpic_status scpic_push(scpic_ctx *ctx, const scpic_particles *parts,
     std::vector<PassOp> ops;
     emit_segment(ops, false, 0.0, els, false);
     for (const PassOp &op : ops)
-        if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, nullptr, nullptr)) return st;
+        if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op)) return st;
     return SCPIC_OK;
 }
 
@@ -576,7 +574,7 @@ scpic_status scpic_deposit(scpic_ctx *ctx, const scpic_particles *parts, int64_t
     PassOp op;
     std::memset(&op, 0, sizeof(op));
     op.deposit = true;
-    if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, nullptr, nullptr)) return st;
+    if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op)) return st;
     const int blocks = parts->n > 0 ? ctx->last_deposit_blocks : 0;
     hipError_t e = launch_reduce(ctx->stream, ctx->dep, blocks, ctx->grid.nx, ctx->grid.ny, rho, n_in);
     if (e != hipSuccess) return fail_hip(e, "reduce launch");
@@ -589,7 +587,7 @@ scpic_status scpic_solve(scpic_ctx *ctx, const int64_t *rho, double scale, void 
     if (scpic_status st = check_ctx(ctx)) return st;
     if (!rho || !ex || !ey) return fail(SCPIC_EINVAL, "rho, ex and ey must be non-NULL");
     if (!std::isfinite(scale)) return fail(SCPIC_EINVAL, "scale must be finite");
-    hipError_t e = launch_solve(ctx->stream, ctx->sw, rho, scale, ex, ey);
+    hipError_t e = launch_solve(ctx->stream, ctx->sw, rho, scale, ex, ey, nullptr);
     if (e != hipSuccess) return fail_hip(e, "solve launch");
     return SCPIC_OK;
 }
@@ -606,7 +604,10 @@ scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void
     std::memset(&op, 0, sizeof(op));
     op.kick = true;
     op.kappa = kappa;
-    return enqueue_pass(ctx, ctx->stream, parts, op, ex, ey);
+    hipError_t e = launch_interleave(ctx->stream, ctx->mixed, true, (void *)ex, (void *)ey, ctx->ef,
+                                     ctx->grid.nx * ctx->grid.ny);
+    if (e != hipSuccess) return fail_hip(e, "field interleave launch");
+    return enqueue_pass(ctx, ctx->stream, parts, op);
 }
 
 scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t kick, double kappa,
@@ -625,7 +626,7 @@ scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t ki
     op.kappa = kappa;
     op.els = pack(els, 0, els.size());
     op.deposit = deposit != 0;
-    return enqueue_pass(ctx, ctx->stream, parts, op, ctx->ex, ctx->ey);
+    return enqueue_pass(ctx, ctx->stream, parts, op);
 }
 
 scpic_status scpic_reduce_solve(scpic_ctx *ctx, double scale)
@@ -640,9 +641,9 @@ scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey)
     g_last_error.clear();
     if (scpic_status st = check_ctx(ctx)) return st;
     if (!ex || !ey) return fail(SCPIC_EINVAL, "ex and ey must be non-NULL");
-    const size_t bytes = field_elem_size(ctx) * (size_t)ctx->grid.nx * ctx->grid.ny;
-    SCPIC_HIP_TRY(hipMemcpyAsync(ex, ctx->ex, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy ex");
-    SCPIC_HIP_TRY(hipMemcpyAsync(ey, ctx->ey, bytes, hipMemcpyDeviceToDevice, ctx->stream), "copy ey");
+    hipError_t e = launch_interleave(ctx->stream, ctx->mixed, false, ex, ey, ctx->ef,
+                                     ctx->grid.nx * ctx->grid.ny);
+    if (e != hipSuccess) return fail_hip(e, "field copy launch");
     return SCPIC_OK;
 }
 

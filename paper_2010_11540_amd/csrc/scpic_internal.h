@@ -23,6 +23,9 @@ constexpr int kMaxPassElements = 12;
 constexpr int kMaxFft = 512;
 constexpr int kMaxCells = 16384;
 
+// Most workgroups a depositing pass may use (one partial grid each).
+constexpr int kMaxPassBlocks = 512;
+
 // Per-block header written by a depositing pass: bounding box of the cells it
 // touched (inclusive; empty when i0 > i1) and how many particles it deposited.
 struct BlockHeader {
@@ -60,10 +63,14 @@ struct ParticlePtrs {
 };
 
 // ---- launchers (particles.hip) ------------------------------------------
+// ef: interleaved node field (Ex, Ey per node), double or float per mixed.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
-                       bool mixed, const void *ex, const void *ey, double kappa,
-                       const PassElements &els, bool deposit, const DepositTarget &dep,
-                       int blocks, int threads);
+                       bool mixed, const void *ef, double kappa, const PassElements &els,
+                       bool deposit, const DepositTarget &dep, int blocks, int threads);
+
+// Copy (ex, ey) into the interleaved field ef, or back.
+hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
+                             void *ef, int ncell);
 
 hipError_t prepare_pass_kernels(size_t lds_bytes);
 
@@ -81,8 +88,10 @@ struct SolveWorkspace {
     void *spec_bx, *spec_by;  // [nx][ny+1] complex, after the column pass
 };
 
+// Field of charge grid q: to separate arrays ex, ey (ef == nullptr) or
+// interleaved into ef.
 hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
-                        void *ex, void *ey);
+                        void *ex, void *ey, void *ef);
 
 // Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
 // the padded 2nx x 2ny periodic kernel.
