@@ -178,10 +178,16 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
  *   SCPIC_OPT_PASS_BLOCKS    workgroups of the particle pass (0 = automatic:
  *                            one per compute unit).
  *   SCPIC_OPT_PASS_THREADS   threads per workgroup of the particle pass
- *                            (256, 512 or 1024; default 1024). */
+ *                            (256, 512 or 1024; default 1024).
+ *   SCPIC_OPT_PASS_VARIANT   loop structure of the particle pass: 0 = all of
+ *                            a thread's particles loaded at once (batches of
+ *                            4), 1 (default) = one particle at a time with the
+ *                            next one's loads in flight.  Results are
+ *                            identical. */
 #define SCPIC_OPT_USE_GRAPH 1
 #define SCPIC_OPT_PASS_BLOCKS 2
 #define SCPIC_OPT_PASS_THREADS 3
+#define SCPIC_OPT_PASS_VARIANT 4
 scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value);
 
 /* Fused particle pass, one launch: optionally kick with the context's

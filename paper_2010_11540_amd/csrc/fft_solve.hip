@@ -1,23 +1,27 @@
-// Grid-side kernels of libscpic for gfx950: the open-boundary Poisson solve
-// as a zero-padded (2nx x 2ny) FFT convolution with the free-space Green's
-// function (Hockney's method), with the centred-difference field taken in the
-// spectrum.  Hand-written radix-4/2 Stockham FFTs in LDS, one wavefront per
-// transform; no vendor FFT library.
+// Grid-side kernels of libscpic for gfx950: the exact reduction of the
+// per-workgroup charge partials and the open-boundary Poisson solve as a
+// zero-padded (2nx x 2ny) FFT convolution with the free-space Green's function
+// (Hockney's method), the centred-difference field taken in the spectrum.
+// Hand-written radix-4/2 Stockham FFTs in LDS; no vendor FFT library.
 //
-// Data flow for a charge grid q (nx x ny int64, rows i along x):
-//   k_rows_fwd   rows i, i+1 packed as one complex sequence of length my
-//                (zero-padded), FFT along y, untangled into the two real-input
-//                half spectra l = 0..ny                     -> A^T [ny+1][nx]
-//   k_cols       per column l: FFT along x (length mx, zero-padded), multiply
-//                by the real Green's spectrum G^(k,l) (normalisation folded
-//                in), then two inverse FFTs: one of -i sin(2 pi k/mx)/dx * Phi
-//                (the x central difference) and one of Phi, scaled by
-//                -i sin(2 pi l/my)/dy (the y central difference); rows
-//                0..nx-1 kept                                -> Bx, By [nx][ny+1]
+// Data flow for a charge grid q (nx x ny, rows i along x):
+//   k_rows_fwd   one workgroup per row i: sum the row's partials exactly
+//                (uint64, + carries) or read a dense int64 row, scale to
+//                rho; the real row zero-padded to my = 2 ny is transformed as
+//                a complex FFT of half length (even/odd samples packed) and
+//                untangled into the half spectrum l = 0..ny   -> A^T [ny+1][nx]
+//   k_cols       per column l: FFT along x (length mx = 2 nx, zero-padded),
+//                multiply by the real Green's spectrum G^(k,l) (inverse-FFT
+//                normalisation folded in), then two inverse FFTs run by two
+//                waves at once: -i sin(2 pi k/mx)/dx * Phi (the x central
+//                difference) and Phi, scaled by -i sin(2 pi l/my)/dy (the y
+//                central difference); rows 0..nx-1 kept -> Bx, By [nx][ny+1]
 //   k_rows_inv   per row i: both half spectra packed as Ex + i Ey, completed
 //                by Hermitian symmetry, one inverse FFT     -> ex, ey [nx][ny]
 // Taking the differences in the spectrum keeps the large constant part of
 // the potential out of the field's rounding, which matters for the FP32 form.
+// Every kernel issues all of its global loads into registers before the
+// first LDS write, so each kernel waits for one round of memory latency.
 #include "scpic_internal.h"
 
 namespace scpic {
@@ -39,6 +43,8 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
 }
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> scale_c(cx<T> a, T s) { return {a.re * s, a.im * s}; }
 // -i * a
 template <typename T>
 __device__ __forceinline__ cx<T> mul_neg_i(cx<T> a) { return {a.im, -a.re}; }
@@ -47,15 +53,17 @@ template <typename T>
 __device__ __forceinline__ cx<T> mul_pos_i(cx<T> a) { return {-a.im, a.re}; }
 
 // Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L) of the sequence in LDS
-// buffer a (length L = 2^log2L), computed by the nthr threads of the
-// workgroup (all of which must call this), ping-ponging with buffer b.
-// Stockham autosort: one radix-2 stage first when log2L is odd, then radix-4
-// stages; each stage reads sub-transform inputs a stride L/r apart, applies
-// the twiddles exp(-2 pi i m k / (Ns r)) and writes the r outputs Ns apart.
-// tw[t] = exp(-2 pi i t / L).  Returns the buffer holding X in natural order.
+// buffer a (length L = 2^log2L), computed by threads tid = 0..nthr-1 of a
+// group, ping-ponging with buffer b.  Every thread of the workgroup must call
+// it the same number of times (it synchronises the workgroup between
+// stages).  Stockham autosort: one radix-2 stage first when log2L is odd, then
+// radix-4 stages; each stage reads sub-transform inputs L/r apart, applies the
+// twiddles exp(-2 pi i m k / (Ns r)) and writes the r outputs Ns apart.
+// tw[t * tws] = exp(-2 pi i t / L).  Returns the buffer holding X in natural
+// order.
 template <typename T>
-__device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *__restrict__ tw,
-                          int tid, int nthr)
+__device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw, int tws, int tid,
+                          int nthr)
 {
     __syncthreads();
     int ns = 1;
@@ -73,10 +81,12 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *__r
         __syncthreads();
     }
     const int q = L >> 2;
+    int span = L >> 2;  // L / (4 ns)
+    if (log2L & 1) span >>= 1;
     while (ns < L) {
         for (int j = tid; j < q; j += nthr) {
             const int k = j & (ns - 1);
-            const int step = (L / (4 * ns)) * k;
+            const int step = span * k * tws;
             const cx<T> a0 = a[j];
             const cx<T> a1 = cmul(a[j + q], tw[step]);
             const cx<T> a2 = cmul(a[j + 2 * q], tw[2 * step]);
@@ -92,52 +102,158 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *__r
         a = b;
         b = t;
         ns *= 4;
+        span >>= 2;
         __syncthreads();
     }
     return a;
 }
 
-constexpr int kFftThreads = 64;
+constexpr int kRowThreads = 1024;  // row-forward: 16 waves share the reduction
+constexpr int kColThreads = 128;   // columns: two waves, one per inverse transform
+constexpr int kInvThreads = 64;    // row-inverse: one wave
+constexpr int kMaxPerThread = kMaxFft / 64;
 
-// Rows 2r and 2r+1 of rho = q * scale, zero-padded to my, as one complex FFT
-// along y; the two real-input spectra are separated with
-//   A0[l] = (Z[l] + conj Z[my-l]) / 2,   A1[l] = -i (Z[l] - conj Z[my-l]) / 2.
-template <typename T>
-__global__ void __launch_bounds__(kFftThreads)
-    k_rows_fwd(const int64_t *__restrict__ q, double scale, int nx, int ny, int my, int log2my,
-               const cx<T> *__restrict__ tw, cx<T> *__restrict__ at)
+// Exact sum of grid row i over the partials of nblocks workgroups plus the
+// carry grid (which is cleared), for the ny cells of the row.  Called by all
+// kRowThreads threads.  Thread t reads 16-byte chunks (4 cells) of the row:
+// ny/4 lanes cover one workgroup's row segment and the kRowThreads/(ny/4)
+// groups of lanes split the workgroups, each issuing all of its loads before
+// adding any (one round of memory latency for <= kReduceChunk workgroups per
+// lane).  Chunks outside a workgroup's bounding box are not read; cells of a
+// chunk outside it are masked.  hdr: the headers staged in LDS; red: LDS
+// scratch of kRowThreads * 4 uint64; carry_v: this cell's carry, loaded by
+// the caller with its first round of loads (cleared here when nonzero).
+// Returns the total of cell tid (tid < ny).
+constexpr int kReduceChunk = 8;
+
+__device__ unsigned long long reduce_row(const DepositTarget &dep, const BlockHeader *hdr,
+                                         unsigned long long *red, int nblocks, int i, int ny,
+                                         int tid, unsigned long long carry_v)
+{
+    const int lanes = ny >> 2;              // 16-byte chunks per row segment
+    const int groups = kRowThreads / lanes;  // ny <= 256 -> at least 16
+    const int grp = tid / lanes, c4 = tid - grp * lanes;
+    const int j0c = c4 * 4;
+    unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
+    for (int b0 = grp; b0 < nblocks; b0 += groups * kReduceChunk) {
+        uint4 v[kReduceChunk];
+        int lo[kReduceChunk], hi[kReduceChunk];
+#pragma unroll
+        for (int u = 0; u < kReduceChunk; ++u) {
+            const int b = b0 + u * groups;
+            bool take = false;
+            lo[u] = 0;
+            hi[u] = -1;
+            if (b < nblocks) {
+                const BlockHeader h = hdr[b];
+                take = i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 && j0c <= h.j1;
+                lo[u] = h.j0;
+                hi[u] = h.j1;
+            }
+            v[u] = take ? *reinterpret_cast<const uint4 *>(row + (size_t)b * ny)
+                        : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceChunk; ++u) {
+            s0 += (j0c + 0 >= lo[u] && j0c + 0 <= hi[u]) ? v[u].x : 0u;
+            s1 += (j0c + 1 >= lo[u] && j0c + 1 <= hi[u]) ? v[u].y : 0u;
+            s2 += (j0c + 2 >= lo[u] && j0c + 2 <= hi[u]) ? v[u].z : 0u;
+            s3 += (j0c + 3 >= lo[u] && j0c + 3 <= hi[u]) ? v[u].w : 0u;
+        }
+    }
+    unsigned long long *mine = red + (size_t)grp * ny + j0c;
+    mine[0] = s0;
+    mine[1] = s1;
+    mine[2] = s2;
+    mine[3] = s3;
+    __syncthreads();
+    unsigned long long t = 0;
+    if (tid < ny) {
+        for (int g = 0; g < groups; ++g) t += red[(size_t)g * ny + tid];
+        t += carry_v;
+        if (carry_v) dep.carry[(size_t)i * ny + tid] = 0ull;
+    }
+    return t;
+}
+
+// Exact int64 charge grid (scpic_deposit): one workgroup per row.
+__global__ void __launch_bounds__(kRowThreads)
+    k_reduce(DepositTarget dep, int nblocks, int nx, int ny, int64_t *__restrict__ q,
+             int64_t *__restrict__ n_in)
+{
+    __shared__ BlockHeader hdr[kMaxPassBlocks];
+    __shared__ unsigned long long red[kRowThreads * 4];
+    const int tid = threadIdx.x, i = blockIdx.x;
+    const unsigned long long cv = tid < ny ? dep.carry[(size_t)i * ny + tid] : 0ull;
+    for (int b = tid; b < nblocks; b += kRowThreads) hdr[b] = dep.header[b];
+    __syncthreads();
+    const unsigned long long t = reduce_row(dep, hdr, red, nblocks, i, ny, tid, cv);
+    if (tid < ny) q[(size_t)i * ny + tid] = (int64_t)t;
+    if (n_in != nullptr && i == 0 && tid < 64) {
+        long long cnt = 0;
+        for (int b = tid; b < nblocks; b += 64) cnt += hdr[b].count;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (tid == 0) *n_in = cnt;
+    }
+}
+
+// Row i of rho (from the partials when FROM_PARTIALS, else from a dense int64
+// grid), real and zero-padded to my: packed z[m] = rho[2m] + i rho[2m+1]
+// (m < ny/2; zero up to ny), Z = FFT_ny(z), then
+//   X[l] = (Z[l] + conj Z[ny-l]) / 2 - i W^l (Z[l] - conj Z[ny-l]) / 2,
+// W = exp(-2 pi i / my), for l = 0..ny.
+template <typename T, bool FROM_PARTIALS>
+__global__ void __launch_bounds__(kRowThreads)
+    k_rows_fwd(DepositTarget dep, int nblocks, const int64_t *__restrict__ q, double scale,
+               int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
+               cx<T> *__restrict__ at)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *a = twl + my;
-    cx<T> *b = a + my;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < my; t += kFftThreads) twl[t] = tw[t];
-    const int i0 = 2 * blockIdx.x;
-    const int64_t *r0 = q + (size_t)i0 * ny;
-    const int64_t *r1 = r0 + ny;
-    for (int j = tid; j < my; j += kFftThreads) {
-        cx<T> z = {T(0), T(0)};
-        if (j < ny) {
-            z.re = (T)((double)r0[j] * scale);
-            z.im = (T)((double)r1[j] * scale);
-        }
-        a[j] = z;
+    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // my entries
+    cx<T> *a = twl + my;                                // ny
+    cx<T> *b = a + ny;                                  // ny
+    T *rho = reinterpret_cast<T *>(b + ny);             // ny
+    __shared__ BlockHeader hdr[FROM_PARTIALS ? kMaxPassBlocks : 1];
+    __shared__ unsigned long long red[FROM_PARTIALS ? kRowThreads * 4 : 1];
+    const int tid = threadIdx.x, i = blockIdx.x;
+    // one round of loads: twiddles, and the headers or the dense row
+    // (my <= 512 and nblocks <= 512 are below kRowThreads)
+    const cx<T> tv = tid < my ? tw[tid] : cx<T>{T(0), T(0)};
+    const int64_t qv = (!FROM_PARTIALS && tid < ny) ? q[(size_t)i * ny + tid] : 0;
+    const unsigned long long cv =
+        (FROM_PARTIALS && tid < ny) ? dep.carry[(size_t)i * ny + tid] : 0ull;
+    BlockHeader hv{};
+    if (FROM_PARTIALS && tid < nblocks) hv = dep.header[tid];
+    if (FROM_PARTIALS && tid < nblocks) hdr[tid] = hv;
+    if (tid < my) twl[tid] = tv;
+    if (FROM_PARTIALS) {
+        __syncthreads();
+        const unsigned long long t = reduce_row(dep, hdr, red, nblocks, i, ny, tid, cv);
+        if (tid < ny) rho[tid] = (T)((double)t * scale);
+    } else {
+        if (tid < ny) rho[tid] = (T)((double)qv * scale);
     }
-    const cx<T> *r = fft_lds(a, b, my, log2my, twl, tid, kFftThreads);
-    for (int l = tid; l <= ny; l += kFftThreads) {
-        const cx<T> zl = r[l];
-        const cx<T> zm = conj(r[(my - l) & (my - 1)]);
+    __syncthreads();
+    const int half = ny;  // complex length: my / 2
+    if (tid < half)
+        a[tid] = (2 * tid + 1 < ny) ? cx<T>{rho[2 * tid], rho[2 * tid + 1]} : cx<T>{T(0), T(0)};
+    const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, kRowThreads);
+    if (tid <= ny) {
+        const int l = tid;
+        const cx<T> zl = Z[l & (half - 1)];
+        const cx<T> zm = conj(Z[(half - l) & (half - 1)]);
         const cx<T> s = zl + zm, d = zl - zm;
-        at[(size_t)l * nx + i0] = {s.re * T(0.5), s.im * T(0.5)};
-        at[(size_t)l * nx + i0 + 1] = mul_neg_i(cx<T>{d.re * T(0.5), d.im * T(0.5)});
+        const cx<T> wd = mul_neg_i(cmul(twl[l], d));
+        at[(size_t)l * nx + i] = scale_c(s + wd, T(0.5));
     }
 }
 
 // Column l of the row spectra: forward FFT along x, times the Green's
-// spectrum, and the two differentiated inverse transforms.
+// spectrum, then the two differentiated inverse transforms, one per wave.
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kColThreads)
     k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
            const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
            const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by)
@@ -147,40 +263,53 @@ __global__ void __launch_bounds__(kFftThreads)
     cx<T> *a = twl + mx;
     cx<T> *b = a + mx;
     cx<T> *c = b + mx;
-    T *gl = reinterpret_cast<T *>(c + mx);
-    T *sxl = gl + mx;
+    cx<T> *d = c + mx;
     const int tid = threadIdx.x;
     const int l = blockIdx.x;
     const cx<T> *col = at + (size_t)l * nx;
     const T *g = ghat_t + (size_t)l * mx;
-    // stage every input of the column in LDS up front (one round of loads)
-    for (int i = tid; i < mx; i += kFftThreads) {
-        twl[i] = tw[i];
-        gl[i] = g[i];
-        sxl[i] = sx[i];
-        a[i] = i < nx ? col[i] : cx<T>{T(0), T(0)};
+    constexpr int kPer = kMaxFft / kColThreads;
+    // every input of the column in one round of loads
+    cx<T> vt[kPer], va[kPer];
+    T vg[kPer], vs[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int k = tid + r * kColThreads;
+        vt[r] = k < mx ? tw[k] : cx<T>{T(0), T(0)};
+        vg[r] = k < mx ? g[k] : T(0);
+        vs[r] = k < mx ? sx[k] : T(0);
+        va[r] = k < nx ? col[k] : cx<T>{T(0), T(0)};
     }
     const T syl = sy[l];
-    cx<T> *r = fft_lds(a, b, mx, log2mx, twl, tid, kFftThreads);
-    // Inverse transforms as conj(FFT(conj(.))): stage the conjugated inputs.
-    for (int k = tid; k < mx; k += kFftThreads) {
-        const T gk = gl[k];
-        const cx<T> phi = {r[k].re * gk, r[k].im * gk};
-        c[k] = conj(phi);
-        const cx<T> dx = mul_neg_i(cx<T>{phi.re * sxl[k], phi.im * sxl[k]});
-        r[k] = conj(dx);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int k = tid + r * kColThreads;
+        if (k < mx) {
+            twl[k] = vt[r];
+            a[k] = va[r];
+        }
     }
-    cx<T> *o = (r == a) ? b : a;
-    const cx<T> *rx = fft_lds(r, o, mx, log2mx, twl, tid, kFftThreads);
-    for (int i = tid; i < nx; i += kFftThreads) bx[(size_t)i * (ny + 1) + l] = conj(rx[i]);
-    // rx may alias r or o; c is untouched.  Use the two free buffers for the
-    // second inverse transform.
-    cx<T> *f0 = c;
-    cx<T> *f1 = (rx == a) ? b : a;
-    const cx<T> *ry = fft_lds(f0, f1, mx, log2mx, twl, tid, kFftThreads);
-    for (int i = tid; i < nx; i += kFftThreads) {
-        const cx<T> p = conj(ry[i]);
-        by[(size_t)i * (ny + 1) + l] = mul_neg_i(cx<T>{p.re * syl, p.im * syl});
+    const cx<T> *r0 = fft_lds(a, b, mx, log2mx, twl, 1, tid, kColThreads);
+    // Inverse transforms as conj(FFT(conj(.))): stage the conjugated inputs,
+    // x difference in c, y part in d.
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int k = tid + r * kColThreads;
+        if (k < mx) {
+            const cx<T> phi = scale_c(r0[k], vg[r]);
+            c[k] = conj(mul_neg_i(scale_c(phi, vs[r])));
+            d[k] = conj(phi);
+        }
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    cx<T> *in = wave ? d : c;
+    cx<T> *tmp = wave ? b : a;
+    const cx<T> *res = fft_lds(in, tmp, mx, log2mx, twl, 1, lane, 64);
+    if (wave == 0) {
+        for (int i = lane; i < nx; i += 64) bx[(size_t)i * (ny + 1) + l] = conj(res[i]);
+    } else {
+        for (int i = lane; i < nx; i += 64)
+            by[(size_t)i * (ny + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
     }
 }
 
@@ -188,7 +317,7 @@ __global__ void __launch_bounds__(kFftThreads)
 // i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kInvThreads)
     k_rows_inv(const cx<T> *__restrict__ bx, const cx<T> *__restrict__ by, int nx, int ny, int my,
                int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
                cx<T> *__restrict__ ef)
@@ -199,20 +328,42 @@ __global__ void __launch_bounds__(kFftThreads)
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
     const int i = blockIdx.x;
-    for (int t = tid; t < my; t += kFftThreads) twl[t] = tw[t];
     const cx<T> *rx = bx + (size_t)i * (ny + 1);
     const cx<T> *ry = by + (size_t)i * (ny + 1);
-    for (int l = tid; l <= ny; l += kFftThreads) {
-        const cx<T> X = rx[l], Y = ry[l];
-        // conjugated inputs for conj(FFT(conj(.)))
-        a[l] = conj(X + mul_pos_i(Y));
-        if (l > 0 && l < ny) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
+    constexpr int kPerT = kMaxFft / kInvThreads;          // twiddles per thread
+    constexpr int kPerL = kMaxFft / 2 / kInvThreads + 1;  // spectrum entries per thread
+    cx<T> vt[kPerT], vx[kPerL], vy[kPerL];
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const int t = tid + r * kInvThreads;
+        vt[r] = t < my ? tw[t] : cx<T>{T(0), T(0)};
     }
-    const cx<T> *r = fft_lds(a, b, my, log2my, twl, tid, kFftThreads);
+#pragma unroll
+    for (int r = 0; r < kPerL; ++r) {
+        const int l = tid + r * kInvThreads;
+        vx[r] = l <= ny ? rx[l] : cx<T>{T(0), T(0)};
+        vy[r] = l <= ny ? ry[l] : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const int t = tid + r * kInvThreads;
+        if (t < my) twl[t] = vt[r];
+    }
+#pragma unroll
+    for (int r = 0; r < kPerL; ++r) {
+        const int l = tid + r * kInvThreads;
+        if (l <= ny) {
+            const cx<T> X = vx[r], Y = vy[r];
+            // conjugated inputs for conj(FFT(conj(.)))
+            a[l] = conj(X + mul_pos_i(Y));
+            if (l > 0 && l < ny) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
+        }
+    }
+    const cx<T> *r = fft_lds(a, b, my, log2my, twl, 1, tid, kInvThreads);
     if (ef) {
-        for (int j = tid; j < ny; j += kFftThreads) ef[(size_t)i * ny + j] = conj(r[j]);
+        for (int j = tid; j < ny; j += kInvThreads) ef[(size_t)i * ny + j] = conj(r[j]);
     } else {
-        for (int j = tid; j < ny; j += kFftThreads) {
+        for (int j = tid; j < ny; j += kInvThreads) {
             const cx<T> z = conj(r[j]);
             ex[(size_t)i * ny + j] = z.re;
             ey[(size_t)i * ny + j] = z.im;
@@ -221,34 +372,61 @@ __global__ void __launch_bounds__(kFftThreads)
 }
 
 template <typename T>
-hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
-                          void *ex, void *ey, void *ef)
+hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *ey, void *ef)
 {
-    const size_t row_lds = 3 * sizeof(cx<T>) * (size_t)w.my;
-    const size_t col_lds = (4 * sizeof(cx<T>) + 2 * sizeof(T)) * (size_t)w.mx;
-    hipLaunchKernelGGL(k_rows_fwd<T>, dim3(w.nx / 2), dim3(kFftThreads), row_lds, s, q, scale,
-                       w.nx, w.ny, w.my, w.log2_my, (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cols<T>, dim3(w.ny + 1), dim3(kFftThreads), col_lds, s,
+    const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)w.mx;
+    const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)w.my;
+    hipLaunchKernelGGL(k_cols<T>, dim3(w.ny + 1), dim3(kColThreads), col_lds, s,
                        (const cx<T> *)w.spec_a, w.nx, w.ny, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
                        (const T *)w.ghat_t, (const T *)w.sx, (const T *)w.sy, (cx<T> *)w.spec_bx,
                        (cx<T> *)w.spec_by);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kFftThreads), row_lds, s,
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kInvThreads), inv_lds, s,
                        (const cx<T> *)w.spec_bx, (const cx<T> *)w.spec_by, w.nx, w.ny, w.my,
                        w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef);
     return hipGetLastError();
 }
 
+template <typename T, bool FROM_PARTIALS>
+hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositTarget &dep,
+                          int nblocks, const int64_t *q, double scale, void *ex, void *ey,
+                          void *ef)
+{
+    const size_t row_lds = sizeof(cx<T>) * (size_t)(w.my + 2 * w.ny) + sizeof(T) * (size_t)w.ny;
+    hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx), dim3(kRowThreads), row_lds, s,
+                       dep, nblocks, q, scale, w.nx, w.ny, w.my, w.log2_my,
+                       (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tail<T>(s, w, ex, ey, ef);
+}
+
 }  // namespace
+
+hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,
+                         int64_t *q, int64_t *n_in)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(nx), dim3(kRowThreads), 0, s, dep, blocks_used, nx, ny, q,
+                       n_in);
+    return hipGetLastError();
+}
 
 hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
                         void *ex, void *ey, void *ef)
 {
-    return w.mixed ? launch_solve_t<float>(s, w, q, scale, ex, ey, ef)
-                   : launch_solve_t<double>(s, w, q, scale, ex, ey, ef);
+    DepositTarget none{};
+    return w.mixed ? launch_solve_t<float, false>(s, w, none, 0, q, scale, ex, ey, ef)
+                   : launch_solve_t<double, false>(s, w, none, 0, q, scale, ex, ey, ef);
+}
+
+hipError_t launch_solve_partials(hipStream_t s, const SolveWorkspace &w, const DepositTarget &dep,
+                                 int blocks_used, double scale, void *ef)
+{
+    return w.mixed ? launch_solve_t<float, true>(s, w, dep, blocks_used, nullptr, scale, nullptr,
+                                                 nullptr, ef)
+                   : launch_solve_t<double, true>(s, w, dep, blocks_used, nullptr, scale, nullptr,
+                                                  nullptr, ef);
 }
 
 }  // namespace scpic

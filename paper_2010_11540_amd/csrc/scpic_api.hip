@@ -73,12 +73,11 @@ struct scpic_ctx {
     int max_blocks = 0;
     int pass_blocks = 0;  // 0 = automatic
     int pass_threads = 1024;
+    int pass_variant = 1;
     bool use_graph = true;
     int last_deposit_blocks = 0;
 
     DepositTarget dep{};
-    int64_t *q = nullptr;
-    int64_t *n_in = nullptr;
     SolveWorkspace sw{};
     void *ef = nullptr;  // internal field, interleaved (Ex, Ey) per node
 
@@ -205,7 +204,8 @@ scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *pa
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
     hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
-                               op.els, op.deposit, c->dep, blocks, c->pass_threads);
+                               op.els, op.deposit, c->dep, blocks, c->pass_threads,
+                               c->pass_variant);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
     if (op.deposit) c->last_deposit_blocks = blocks;
     return SCPIC_OK;
@@ -213,10 +213,7 @@ scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *pa
 
 scpic_status enqueue_grid_phase(scpic_ctx *c, hipStream_t s, double scale)
 {
-    hipError_t e = launch_reduce(s, c->dep, c->last_deposit_blocks, c->grid.nx, c->grid.ny, c->q,
-                                 nullptr);
-    if (e != hipSuccess) return fail_hip(e, "reduce launch");
-    e = launch_solve(s, c->sw, c->q, scale, nullptr, nullptr, c->ef);
+    hipError_t e = launch_solve_partials(s, c->sw, c->dep, c->last_deposit_blocks, scale, c->ef);
     if (e != hipSuccess) return fail_hip(e, "solve launch");
     return SCPIC_OK;
 }
@@ -277,6 +274,7 @@ std::vector<unsigned char> graph_key(const scpic_ctx *c, const scpic_particles *
     put(p, sizeof(*p));
     put(&c->pass_blocks, sizeof(c->pass_blocks));
     put(&c->pass_threads, sizeof(c->pass_threads));
+    put(&c->pass_variant, sizeof(c->pass_variant));
     for (const PassOp &op : ops) {
         put(&op.kick, sizeof(op.kick));
         put(&op.kappa, sizeof(op.kappa));
@@ -428,7 +426,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     c->max_blocks = std::min(2 * c->n_cu, kMaxPassBlocks);
     const int nx = grid->nx, ny = grid->ny, ncell = nx * ny;
     const size_t lds = sizeof(uint32_t) * (size_t)ncell;
-    if (lds + 64 > prop.sharedMemPerBlock)
+    if (lds + 256 > prop.sharedMemPerBlock)
         return fail(SCPIC_EUNSUPPORTED, "charge grid does not fit the workgroup's LDS");
     const size_t fe = field_elem_size(c);
     const size_t ce = 2 * fe;
@@ -442,8 +440,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     ALLOC(c->dep.partial, sizeof(uint32_t) * (size_t)c->max_blocks * ncell);
     ALLOC(c->dep.header, sizeof(BlockHeader) * (size_t)c->max_blocks);
     ALLOC(c->dep.carry, sizeof(unsigned long long) * (size_t)ncell);
-    ALLOC(c->q, sizeof(int64_t) * (size_t)ncell);
-    ALLOC(c->n_in, sizeof(int64_t));
+    c->dep.max_blocks = c->max_blocks;
     c->sw.nx = nx;
     c->sw.ny = ny;
     c->sw.mx = 2 * nx;
@@ -466,7 +463,8 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     SCPIC_HIP_TRY(hipMemset(c->ef, 0, 2 * fe * ncell), "hipMemset");
     st = c->mixed ? upload_tables<float>(c) : upload_tables<double>(c);
     if (st) return st;
-    SCPIC_HIP_TRY(prepare_pass_kernels(lds), "hipFuncSetAttribute");
+    // the pass's static LDS is a few words; keep 256 bytes for it
+    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock - 256), "hipFuncSetAttribute");
     SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     return SCPIC_OK;
 }
@@ -537,6 +535,10 @@ scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
         if (value < 0 || value > ctx->max_blocks)
             return fail(SCPIC_EINVAL, "pass blocks must be in [0, " + std::to_string(ctx->max_blocks) + "]");
         ctx->pass_blocks = (int)value;
+        return SCPIC_OK;
+    case SCPIC_OPT_PASS_VARIANT:
+        if (value < 0 || value > 1) return fail(SCPIC_EINVAL, "pass variant must be 0 or 1");
+        ctx->pass_variant = (int)value;
         return SCPIC_OK;
     case SCPIC_OPT_PASS_THREADS:
         if (value != 256 && value != 512 && value != 1024)

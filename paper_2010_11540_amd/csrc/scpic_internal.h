@@ -49,11 +49,15 @@ struct PassElements {
     double p[kMaxPassElements][16];
 };
 
-// Device-side buffers of the charge partials.
+// Device-side buffers of the charge partials.  Workgroup b of a depositing
+// pass writes the cells (i, j) of its bounding box to
+// partial[(i * max_blocks + b) * ny + j]: the partials of one grid row are
+// contiguous, so the row that reduces them reads one contiguous span.
 struct DepositTarget {
-    uint32_t *partial;            // [blocks][nx*ny] bounding-box-packed cells
-    BlockHeader *header;          // [blocks]
+    uint32_t *partial;            // [nx][max_blocks][ny]
+    BlockHeader *header;          // [max_blocks]
     unsigned long long *carry;    // [nx*ny] whole 2^32 overflows of LDS cells
+    int32_t max_blocks;
 };
 
 struct ParticlePtrs {
@@ -66,7 +70,8 @@ struct ParticlePtrs {
 // ef: interleaved node field (Ex, Ey per node), double or float per mixed.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
-                       bool deposit, const DepositTarget &dep, int blocks, int threads);
+                       bool deposit, const DepositTarget &dep, int blocks, int threads,
+                       int variant);
 
 // Copy (ex, ey) into the interleaved field ef, or back.
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
@@ -74,6 +79,8 @@ hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, voi
 
 hipError_t prepare_pass_kernels(size_t lds_bytes);
 
+// Exact charge grid q (int64) and deposited count from the partials of the
+// last depositing pass (blocks_used workgroups); clears the carry grid.
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,
                          int64_t *q, int64_t *n_in);
 
@@ -92,6 +99,11 @@ struct SolveWorkspace {
 // interleaved into ef.
 hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q, double scale,
                         void *ex, void *ey, void *ef);
+
+// Field straight from the partials of the last depositing pass (the exact
+// integer reduction is fused into the first FFT stage), interleaved into ef.
+hipError_t launch_solve_partials(hipStream_t s, const SolveWorkspace &w, const DepositTarget &dep,
+                                 int blocks_used, double scale, void *ef);
 
 // Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
 // the padded 2nx x 2ny periodic kernel.

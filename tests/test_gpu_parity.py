@@ -94,15 +94,17 @@ def test_deposit_edges_nan_inf_and_lost(gpu, orc):
         assert int(n_in.item()) == n_ref == 3
 
 
-@pytest.mark.parametrize("threads,blocks", [(256, 0), (512, 7), (1024, 1), (1024, 0)])
-def test_deposit_independent_of_launch_shape_and_repeatable(gpu, orc, threads, blocks):
-    _say(f"deposit launch shape threads={threads} blocks={blocks}")
+@pytest.mark.parametrize("threads,blocks,variant", [(256, 0, 0), (512, 7, 0), (1024, 1, 0),
+                                                    (1024, 0, 0), (1024, 0, 1), (256, 3, 1)])
+def test_deposit_independent_of_launch_shape_and_repeatable(gpu, orc, threads, blocks, variant):
+    _say(f"deposit launch shape threads={threads} blocks={blocks} variant={variant}")
     g = inputs.make_grid(128)
     p = inputs.gaussian_beam(300_001, 11)
     q_ref, _ = orc.deposit(inputs.copy_parts(p), g)
     with gpu.Context(g) as ctx:
         ctx.set_option(gpu.OPT_PASS_THREADS, threads)
         ctx.set_option(gpu.OPT_PASS_BLOCKS, blocks)
+        ctx.set_option(gpu.OPT_PASS_VARIANT, variant)
         d = _dev(p)
         r1, _ = ctx.deposit(d)
         r2, _ = ctx.deposit(d)
@@ -202,14 +204,15 @@ def _turn_err(h, ref):
     return max(np.abs(h[k] - ref[k]).max() / ref[k].std() for k in COORDS)
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_small_workload_one_turn_fp64(gpu, orc, use_graph):
-    _say(f"track small workload 1 turn fp64 graph={use_graph}")
+@pytest.mark.parametrize("use_graph,variant", [(True, 0), (False, 0), (True, 1)])
+def test_small_workload_one_turn_fp64(gpu, orc, use_graph, variant):
+    _say(f"track small workload 1 turn fp64 graph={use_graph} variant={variant}")
     w = inputs.workload("small")
     ref = inputs.copy_parts(w["parts"])
     orc.track(ref, w["grid"], w["lattice"], 1)
     with gpu.Context(w["grid"]) as ctx:
         ctx.set_option(gpu.OPT_USE_GRAPH, int(use_graph))
+        ctx.set_option(gpu.OPT_PASS_VARIANT, variant)
         d = _dev(w["parts"])
         ctx.track(d, w["lattice"], 1)
         h = _host(d)
@@ -260,14 +263,22 @@ def test_turn_starting_and_ending_with_elements_and_lost_particles(gpu, orc):
     assert _turn_err(h, ref) <= 1e-10
 
 
-def test_production_workload_one_turn_fp64(gpu, orc):
-    """Full production shape (1e6 particles, 128^2, 100 SC steps with 4x4
-    maps and sextupoles), the launch configuration the benchmark times."""
-    _say("track production workload 1 turn fp64 (1e6 particles)")
+@pytest.fixture(scope="module")
+def production_one_turn_reference(orc):
     w = inputs.workload("production")
     ref = inputs.copy_parts(w["parts"])
     orc.track(ref, w["grid"], w["lattice"], 1)
+    return w, ref
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_production_workload_one_turn_fp64(gpu, production_one_turn_reference, variant):
+    """Full production shape (1e6 particles, 128^2, 100 SC steps with 4x4
+    maps and sextupoles), the launch configuration the benchmark times."""
+    _say(f"track production workload 1 turn fp64 (1e6 particles) variant={variant}")
+    w, ref = production_one_turn_reference
     with gpu.Context(w["grid"]) as ctx:
+        ctx.set_option(gpu.OPT_PASS_VARIANT, variant)
         d = _dev(w["parts"])
         ctx.track(d, w["lattice"], 1)
         h = _host(d)
