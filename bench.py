@@ -45,7 +45,6 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
     ap.add_argument("--pass-threads", type=int, default=0)
     ap.add_argument("--pass-blocks", type=int, default=0)
-    ap.add_argument("--pass-variant", type=int, default=-1)
     ap.add_argument("--pass-reps", type=int, default=200, help="standalone pass launches timed")
     ap.add_argument("--cpu-seconds", type=float, default=6.0,
                     help="wall-clock budget of the CPU oracle sample")
@@ -151,8 +150,6 @@ def main():
         ctx.set_option(scpic.OPT_PASS_THREADS, args.pass_threads)
     if args.pass_blocks:
         ctx.set_option(scpic.OPT_PASS_BLOCKS, args.pass_blocks)
-    if args.pass_variant >= 0:
-        ctx.set_option(scpic.OPT_PASS_VARIANT, args.pass_variant)
     d = scpic.to_device(w["parts"])
     torch.cuda.synchronize()
 

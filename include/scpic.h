@@ -60,7 +60,7 @@ typedef int32_t scpic_status;
  * index i*ny + j (i along x).  A particle belongs to the domain when
  * 0 <= (x - x_min) * (1/dx) < nx - 1 and likewise in y (each product and the
  * reciprocal evaluated in FP64, correctly rounded); a NaN coordinate does not.
- * Supported: nx, ny powers of two in [8, 256] and nx * ny <= 16384. */
+ * Supported: nx, ny powers of two in [8, 256]. */
 typedef struct {
     int32_t nx, ny;
     double x_min, y_min, dx, dy;
@@ -68,12 +68,19 @@ typedef struct {
 
 /* ---- particles --------------------------------------------------------- */
 /* Structure of arrays, n entries each, device, contiguous FP64.
+ * w (device, n floats, may be NULL): per-particle kick weight w_p; a kick
+ * adds kappa * w_p * E (w_p = 1 when NULL).  This is the 2.5D long-bunch
+ * form of Sec. IV (eq. poisson3D, eq. pot2): the transverse field of the
+ * whole beam's transverse distribution, scaled by the line density
+ * lambda(z_p) at the particle (w_p = lambda(z_p) / lambda_peak).  The deposit
+ * is unweighted.
  * lost (device, n bytes, may be NULL): nonzero marks a particle that has left
  * the grid domain at a deposit or kick; a lost particle is frozen (no push,
  * kick or deposit) and keeps its last coordinates.  With lost == NULL,
  * particles outside the domain simply take no part in deposit and kick. */
 typedef struct {
     double *x, *px, *y, *py;
+    const float *w;
     uint8_t *lost;
     int64_t n;
 } scpic_particles;
@@ -179,15 +186,10 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
  *                            one per compute unit).
  *   SCPIC_OPT_PASS_THREADS   threads per workgroup of the particle pass
  *                            (256, 512 or 1024; default 1024).
- *   SCPIC_OPT_PASS_VARIANT   loop structure of the particle pass: 0 = all of
- *                            a thread's particles loaded at once (batches of
- *                            4), 1 (default) = one particle at a time with the
- *                            next one's loads in flight.  Results are
- *                            identical. */
+ * Results do not depend on the launch shape. */
 #define SCPIC_OPT_USE_GRAPH 1
 #define SCPIC_OPT_PASS_BLOCKS 2
 #define SCPIC_OPT_PASS_THREADS 3
-#define SCPIC_OPT_PASS_VARIANT 4
 scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value);
 
 /* Fused particle pass, one launch: optionally kick with the context's

@@ -19,7 +19,8 @@ What each function follows (arXiv:2010.11540):
               direct sum over charged nodes.
   field       E = -grad(u) (Sec. IV-C), by centred differences on the nodes.
   kick        Sec. IV: transverse kick proportional to the field at the
-              particle times the distance since the previous kick.
+              particle times the distance since the previous kick, and (2.5D
+              form) to the line density at the particle relative to its peak.
 """
 from __future__ import annotations
 
@@ -37,7 +38,8 @@ _LIB = _HERE / "liborc.so"
 LIN2X2, LIN4X4, SEXT_THIN, SC = 1, 2, 3, 4
 CHARGE_ONE = 1 << 24
 
-_C_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+_C_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+            "-Wall", "-Wshadow", "-Werror"]
 
 
 def build(force: bool = True) -> Path:
@@ -70,13 +72,14 @@ def lib():
         L.orc_potential.restype = None
         L.orc_field.argtypes = [vp, i32, i32, dbl, dbl, vp, vp]
         L.orc_field.restype = None
-        L.orc_kick.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp, dbl]
+        L.orc_kick.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp,
+                               dbl]
         L.orc_kick.restype = None
-        L.orc_space_charge.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
+        L.orc_space_charge.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
                                        dbl, dbl, vp, vp]
         L.orc_space_charge.restype = i64
-        L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, vp, vp,
-                                i32]
+        L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, vp,
+                                vp, i32]
         L.orc_track.restype = None
         _lib = L
     return _lib
@@ -156,13 +159,24 @@ def solve(q: np.ndarray, scale: float, grid) -> tuple[np.ndarray, np.ndarray]:
     return field(potential(q, scale, grid), grid)
 
 
+def _weights(parts):
+    w = parts.get("w")
+    if w is None:
+        return None
+    if w.dtype != np.float32 or not w.flags.c_contiguous:
+        raise TypeError("w must be a contiguous float32 array")
+    return w
+
+
 def kick(parts: dict, grid, ex: np.ndarray, ey: np.ndarray, kappa: float) -> None:
-    """In place: gather the node field with the deposit weights, p += kappa * E."""
+    """In place: gather the node field with the deposit weights,
+    p += kappa * w_p * E (w_p = parts['w'] when present, else 1)."""
     n = parts["x"].shape[0]
     ex = _f64(ex)
     ey = _f64(ey)
     lib().orc_kick(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
-                   _ptr(parts.get("lost")), *_grid_args(grid), _ptr(ex), _ptr(ey), float(kappa))
+                   _ptr(parts.get("lost")), _ptr(_weights(parts)), *_grid_args(grid), _ptr(ex),
+                   _ptr(ey), float(kappa))
 
 
 def space_charge(parts: dict, grid, scale: float, kappa: float):
@@ -172,8 +186,9 @@ def space_charge(parts: dict, grid, scale: float, kappa: float):
     ey = np.zeros(nx * ny)
     n = parts["x"].shape[0]
     n_in = lib().orc_space_charge(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
-                                  _ptr(parts["py"]), _ptr(parts.get("lost")), *_grid_args(grid),
-                                  float(scale), float(kappa), _ptr(ex), _ptr(ey))
+                                  _ptr(parts["py"]), _ptr(parts.get("lost")),
+                                  _ptr(_weights(parts)), *_grid_args(grid), float(scale),
+                                  float(kappa), _ptr(ex), _ptr(ey))
     return ex, ey, int(n_in)
 
 
@@ -182,5 +197,5 @@ def track(parts: dict, grid, elements, n_turns: int) -> None:
     kind, par = _elements(elements)
     n = parts["x"].shape[0]
     lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
-                    _ptr(parts.get("lost")), *_grid_args(grid), len(kind), _ptr(kind), _ptr(par),
-                    int(n_turns))
+                    _ptr(parts.get("lost")), _ptr(_weights(parts)), *_grid_args(grid), len(kind),
+                    _ptr(kind), _ptr(par), int(n_turns))

@@ -214,7 +214,11 @@ double orc_green(int di, int dj, double dx, double dy)
 /* Potential phi = G (*) rho by the direct sum over all charged nodes, at the
  * nodes i = -1..nx, j = -1..ny (one ring of nodes around the grid, needed by
  * the centred differences of the field).  rho = q * scale.
- * phi is (nx+2) x (ny+2), row-major, phi[(i+1)*(ny+2) + (j+1)]. */
+ * phi is (nx+2) x (ny+2), row-major, phi[(i+1)*(ny+2) + (j+1)].
+ * The sum is accumulated in extended precision (long double): the field is a
+ * difference of neighbouring potentials two orders of magnitude smaller than
+ * the potentials themselves, so FP64 accumulation of thousands of terms would
+ * leave the oracle's own rounding near 1e-12 of the field on fine grids. */
 void orc_potential(const int64_t *q, double scale, int nx, int ny, double dx, double dy, double *phi)
 {
     /* G depends only on |di|, |dj| <= nx, ny: tabulate it once. */
@@ -228,14 +232,14 @@ void orc_potential(const int64_t *q, double scale, int nx, int ny, double dx, do
     for (ti = 0; ti < targets; ++ti) {
         int i = (int)(ti / (ny + 2)) - 1;
         int j = (int)(ti % (ny + 2)) - 1;
-        double s = 0.0;
+        long double s = 0.0L;
         for (int k = 0; k < nx; ++k)
             for (int l = 0; l < ny; ++l) {
                 int64_t c = q[(int64_t)k * ny + l];
                 if (c == 0) continue;
-                s += G[abs(i - k) * gy + abs(j - l)] * ((double)c * scale);
+                s += (long double)G[abs(i - k) * gy + abs(j - l)] * ((long double)c * scale);
             }
-        phi[ti] = s;
+        phi[ti] = (double)s;
     }
     free(G);
 }
@@ -254,13 +258,16 @@ void orc_field(const double *phi, int nx, int ny, double dx, double dy, double *
 }
 
 /* Interpolate the node field to each alive particle with the same four
- * weights as the deposit and kick its momenta: p += kappa * E.  A particle
- * outside the domain is marked lost instead.  (Sec. IV: the transverse kick is
- * proportional to the field times the distance since the previous
- * space-charge location; kappa carries that length and the perveance.) */
+ * weights as the deposit and kick its momenta: p += kappa * w_p * E, with the
+ * particle's weight w_p = wt[p] (1 when wt is NULL).  A particle outside the domain is
+ * marked lost instead.  (Sec. IV: the transverse kick is proportional to the
+ * line density at the particle times the field of the transverse
+ * distribution times the distance since the previous space-charge location;
+ * kappa carries that length and the perveance, w_p the line density relative
+ * to its peak.) */
 void orc_kick(int64_t n, const double *x, double *px, const double *y, double *py, uint8_t *lost,
-              int nx, int ny, double x_min, double y_min, double dx, double dy, const double *ex,
-              const double *ey, double kappa)
+              const float *wt, int nx, int ny, double x_min, double y_min, double dx, double dy,
+              const double *ex, const double *ey, double kappa)
 {
     orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
     int64_t p;
@@ -278,8 +285,9 @@ void orc_kick(int64_t n, const double *x, double *px, const double *y, double *p
                        (double)w[3] * ex[c11]) / ORC_CHARGE_ONE;
         double eyp = ((double)w[0] * ey[c00] + (double)w[1] * ey[c10] + (double)w[2] * ey[c01] +
                       (double)w[3] * ey[c11]) / ORC_CHARGE_ONE;
-        px[p] += kappa * exp_;
-        py[p] += kappa * eyp;
+        double k = wt ? kappa * (double)wt[p] : kappa;
+        px[p] += k * exp_;
+        py[p] += k * eyp;
     }
 }
 
@@ -288,8 +296,8 @@ void orc_kick(int64_t n, const double *x, double *px, const double *y, double *p
  * for N0 initial macro-particles, so the total charge is 1).  ex/ey, when not
  * NULL, receive the node field.  Returns the number of particles deposited. */
 int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
-                         int nx, int ny, double x_min, double y_min, double dx, double dy,
-                         double scale, double kappa, double *ex_out, double *ey_out)
+                         const float *wt, int nx, int ny, double x_min, double y_min, double dx,
+                         double dy, double scale, double kappa, double *ex_out, double *ey_out)
 {
     int64_t cells = (int64_t)nx * ny;
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)cells);
@@ -299,7 +307,7 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
     int64_t n_in = orc_deposit(n, x, y, lost, nx, ny, x_min, y_min, dx, dy, q);
     orc_potential(q, scale, nx, ny, dx, dy, phi);
     orc_field(phi, nx, ny, dx, dy, ex, ey);
-    orc_kick(n, x, px, y, py, lost, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
+    orc_kick(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
     if (!ex_out) free(ex);
     if (!ey_out) free(ey);
     free(phi);
@@ -311,15 +319,15 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
  * elements are pushed, each space-charge element runs the full step above with
  * its own kappa.  The charge scale is 1/(2^24 n): n is the initial particle
  * count, so lost particles take their charge with them. */
-void orc_track(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost, int nx,
-               int ny, double x_min, double y_min, double dx, double dy, int n_el,
-               const int32_t *kind, const double *par, int n_turns)
+void orc_track(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
+               const float *wt, int nx, int ny, double x_min, double y_min, double dx, double dy,
+               int n_el, const int32_t *kind, const double *par, int n_turns)
 {
     double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
     for (int t = 0; t < n_turns; ++t)
         for (int e = 0; e < n_el; ++e) {
             if (kind[e] == ORC_SC)
-                orc_space_charge(n, x, px, y, py, lost, nx, ny, x_min, y_min, dx, dy, scale,
+                orc_space_charge(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale,
                                  par[16 * e], NULL, NULL);
             else
                 orc_push(n, x, px, y, py, lost, 1, kind + e, par + 16 * e);

@@ -139,20 +139,19 @@ __device__ unsigned long long reduce_row(const DepositTarget &dep, const BlockHe
     for (int b0 = grp; b0 < nblocks; b0 += groups * kReduceChunk) {
         uint4 v[kReduceChunk];
         int lo[kReduceChunk], hi[kReduceChunk];
+        // Branch-free: every lane issues its loads back to back (a chunk
+        // outside a box is read from workgroup 0's slice, always valid, and
+        // masked), so the compiler does not wait between them.
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
             const int b = b0 + u * groups;
-            bool take = false;
-            lo[u] = 0;
-            hi[u] = -1;
-            if (b < nblocks) {
-                const BlockHeader h = hdr[b];
-                take = i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 && j0c <= h.j1;
-                lo[u] = h.j0;
-                hi[u] = h.j1;
-            }
-            v[u] = take ? *reinterpret_cast<const uint4 *>(row + (size_t)b * ny)
-                        : make_uint4(0, 0, 0, 0);
+            const int bc = b < nblocks ? b : 0;
+            const BlockHeader h = hdr[bc];
+            const bool take = b < nblocks && i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 &&
+                              j0c <= h.j1;
+            lo[u] = take ? h.j0 : 0;
+            hi[u] = take ? h.j1 : -1;
+            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(take ? bc : 0) * ny);
         }
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {

@@ -73,7 +73,6 @@ struct scpic_ctx {
     int max_blocks = 0;
     int pass_blocks = 0;  // 0 = automatic
     int pass_threads = 1024;
-    int pass_variant = 1;
     bool use_graph = true;
     int last_deposit_blocks = 0;
 
@@ -134,6 +133,7 @@ ParticlePtrs to_ptrs(const scpic_particles *p)
     r.px = p->px;
     r.y = p->y;
     r.py = p->py;
+    r.w = p->w;
     r.lost = p->lost;
     r.n = p->n;
     return r;
@@ -204,8 +204,7 @@ scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *pa
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
     hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
-                               op.els, op.deposit, c->dep, blocks, c->pass_threads,
-                               c->pass_variant);
+                               op.els, op.deposit, c->dep, blocks, c->pass_threads);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
     if (op.deposit) c->last_deposit_blocks = blocks;
     return SCPIC_OK;
@@ -274,7 +273,6 @@ std::vector<unsigned char> graph_key(const scpic_ctx *c, const scpic_particles *
     put(p, sizeof(*p));
     put(&c->pass_blocks, sizeof(c->pass_blocks));
     put(&c->pass_threads, sizeof(c->pass_threads));
-    put(&c->pass_variant, sizeof(c->pass_variant));
     for (const PassOp &op : ops) {
         put(&op.kick, sizeof(op.kick));
         put(&op.kappa, sizeof(op.kappa));
@@ -426,8 +424,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     c->max_blocks = std::min(2 * c->n_cu, kMaxPassBlocks);
     const int nx = grid->nx, ny = grid->ny, ncell = nx * ny;
     const size_t lds = sizeof(uint32_t) * (size_t)ncell;
-    if (lds + 256 > prop.sharedMemPerBlock)
-        return fail(SCPIC_EUNSUPPORTED, "charge grid does not fit the workgroup's LDS");
+    (void)lds;
     const size_t fe = field_elem_size(c);
     const size_t ce = 2 * fe;
     scpic_status st;
@@ -459,7 +456,9 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     ALLOC(c->ef, 2 * fe * ncell);
 #undef ALLOC
     SCPIC_HIP_TRY(hipMemset(c->dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
-    SCPIC_HIP_TRY(hipMemset(c->dep.header, 0, sizeof(BlockHeader) * c->max_blocks), "hipMemset");
+    // headers start "unknown" (all -1): the first deposit uses the whole grid
+    // as its LDS tile when it fits
+    SCPIC_HIP_TRY(hipMemset(c->dep.header, 0xff, sizeof(BlockHeader) * c->max_blocks), "hipMemset");
     SCPIC_HIP_TRY(hipMemset(c->ef, 0, 2 * fe * ncell), "hipMemset");
     st = c->mixed ? upload_tables<float>(c) : upload_tables<double>(c);
     if (st) return st;
@@ -492,7 +491,7 @@ scpic_status scpic_create(scpic_ctx **out, const scpic_grid *grid, int32_t preci
     if (!is_pow2_in(grid->nx, 8, 256) || !is_pow2_in(grid->ny, 8, 256))
         return fail(SCPIC_EUNSUPPORTED, "nx and ny must be powers of two in [8, 256]");
     if ((int64_t)grid->nx * grid->ny > kMaxCells)
-        return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 16384 (LDS charge grid)");
+        return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 65536");
     scpic_ctx *c = new (std::nothrow) scpic_ctx();
     if (!c) return fail(SCPIC_ENOMEM, "host allocation failed");
     scpic_status st = create_impl(c, grid, precision, hip_stream);
@@ -535,10 +534,6 @@ scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
         if (value < 0 || value > ctx->max_blocks)
             return fail(SCPIC_EINVAL, "pass blocks must be in [0, " + std::to_string(ctx->max_blocks) + "]");
         ctx->pass_blocks = (int)value;
-        return SCPIC_OK;
-    case SCPIC_OPT_PASS_VARIANT:
-        if (value < 0 || value > 1) return fail(SCPIC_EINVAL, "pass variant must be 0 or 1");
-        ctx->pass_variant = (int)value;
         return SCPIC_OK;
     case SCPIC_OPT_PASS_THREADS:
         if (value != 256 && value != 512 && value != 1024)

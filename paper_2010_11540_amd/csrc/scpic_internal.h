@@ -19,9 +19,9 @@ constexpr double kChargeOne = 16777216.0;  // 2^24
 // Elements a single particle pass can carry in its kernel arguments.
 constexpr int kMaxPassElements = 12;
 
-// Largest FFT length (2 * largest grid side) and grid cells held in LDS.
+// Largest FFT length (2 * largest grid side) and largest grid.
 constexpr int kMaxFft = 512;
-constexpr int kMaxCells = 16384;
+constexpr int kMaxCells = 65536;
 
 // Most workgroups a depositing pass may use (one partial grid each).
 constexpr int kMaxPassBlocks = 512;
@@ -62,6 +62,7 @@ struct DepositTarget {
 
 struct ParticlePtrs {
     double *x, *px, *y, *py;
+    const float *w;  // per-particle kick weight (2.5D line density), may be null
     uint8_t *lost;
     int64_t n;
 };
@@ -70,8 +71,7 @@ struct ParticlePtrs {
 // ef: interleaved node field (Ex, Ey per node), double or float per mixed.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
-                       bool deposit, const DepositTarget &dep, int blocks, int threads,
-                       int variant);
+                       bool deposit, const DepositTarget &dep, int blocks, int threads);
 
 // Copy (ex, ey) into the interleaved field ef, or back.
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,

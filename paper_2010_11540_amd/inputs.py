@@ -89,6 +89,30 @@ def kv_beam(n: int, seed: int, a=4e-3, b=2e-3, beta_x=1.0, beta_y=1.0, lost: boo
     return parts
 
 
+def line_density_weights(z: np.ndarray, z_half: float, bins: int = 128) -> np.ndarray:
+    """Static 2.5D kick weights: the line density lambda(z) of the bunch as a
+    histogram of z over [-z_half, z_half] (the paper uses 128 bins, Sec. IV),
+    divided by its peak, read at each particle's bin."""
+    counts, edges = np.histogram(z, bins=bins, range=(-z_half, z_half))
+    k = np.clip(((z + z_half) / (2 * z_half) * bins).astype(np.int64), 0, bins - 1)
+    return np.ascontiguousarray(counts[k] / counts.max(), dtype=np.float32)
+
+
+def long_bunch_kv(n: int, seed: int, a=4e-3, b=2e-3, beta=1.0, sigma_z=0.25, z_half=0.5) -> dict:
+    """KV transverse beam with a Gaussian longitudinal profile (rms sigma_z in
+    bucket units, truncated to +-z_half) turned into per-particle kick weights."""
+    parts = kv_beam(n, seed, a, b, beta, beta)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    z = rng.standard_normal(2 * n + 1000) * sigma_z
+    z = z[np.abs(z) < z_half][:n]
+    while z.shape[0] < n:  # practically never: the cut keeps ~95% of draws
+        more = rng.standard_normal(n) * sigma_z
+        z = np.concatenate([z, more[np.abs(more) < z_half]])[:n]
+    parts["w"] = line_density_weights(z, z_half)
+    parts["z"] = np.ascontiguousarray(z)
+    return parts
+
+
 def uniform_in_box(n: int, seed: int, grid: dict, margin: float = 0.0) -> dict:
     """Positions uniform over the grid's domain (shrunk by margin cells)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -206,6 +230,12 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
     production 1e6 Gaussian, 128^2 grid, 100 block-diagonal 4x4 maps plus 10
                thin sextupoles (k2L = 5 m^-2) and 100 SC kicks per turn,
                dnu = -0.2; 100 turns.
+    large      1e7 particles, KV 2:1 (a = 4 mm, b = 2 mm) with Gaussian z
+               (sigma = 0.25 bucket, cut at +-0.5) as 128-bin line-density
+               kick weights, 256^2 grid over +-12 x +-6 mm (+-6 rms), 200
+               segments without sextupoles, kappa for dnu_y = -0.2 at the
+               bunch peak (K C = 2 pi (eps_y + sqrt(eps_x eps_y)) 0.2, edge
+               emittances); 1000 turns.
     """
     eps = 1e-6  # rms emittance (1 mm x 1 mrad)
     if name == "small":
@@ -221,6 +251,16 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
         lat = ring(4.2, 4.3, 100, kappa_for_tune_shift(-0.2, eps, 100), four_by_four=True,
                    k2l=5.0, sext_every=10)
         turns = 100
+    elif name == "large":
+        n = 10_000_000 if n is None else n
+        seed = SEED_BASE + 5 if seed is None else seed
+        grid = make_grid(256, 256, 12e-3, 6e-3)
+        a, b = 4e-3, 2e-3
+        eps_x, eps_y = a * a, b * b  # edge emittances at beta = 1 m
+        kc = 2 * math.pi * (eps_y + math.sqrt(eps_x * eps_y)) * 0.2
+        lat = ring(4.2, 4.3, 200, kc / 200)
+        return {"name": name, "parts": long_bunch_kv(n, seed, a, b), "grid": grid, "lattice": lat,
+                "turns": 1000, "n": n, "seed": seed}
     else:
         raise ValueError(f"unknown workload {name!r}")
     return {"name": name, "parts": gaussian_beam(n, seed), "grid": grid, "lattice": lat,

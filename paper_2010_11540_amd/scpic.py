@@ -23,7 +23,7 @@ _LIB_PATH = Path(__file__).resolve().parent / "libscpic.so"
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
-OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS, OPT_PASS_VARIANT = 1, 2, 3, 4
+OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS = 1, 2, 3
 
 # every function the header declares, for load checks
 EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
@@ -39,7 +39,8 @@ class Grid(ctypes.Structure):
 
 class Particles(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("px", ctypes.c_void_p), ("y", ctypes.c_void_p),
-                ("py", ctypes.c_void_p), ("lost", ctypes.c_void_p), ("n", ctypes.c_int64)]
+                ("py", ctypes.c_void_p), ("w", ctypes.c_void_p), ("lost", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
 
 
 class ScpicError(RuntimeError):
@@ -118,7 +119,13 @@ def particles_struct(parts: dict) -> Particles:
                 and lost.shape == (n,)):
             raise TypeError("lost must be a contiguous uint8 CUDA tensor of length n")
         lp = lost.data_ptr()
-    return Particles(*ptrs, lp, n)
+    w = parts.get("w")
+    wp = None
+    if w is not None:
+        if not (w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.shape == (n,)):
+            raise TypeError("w must be a contiguous float32 CUDA tensor of length n")
+        wp = w.data_ptr()
+    return Particles(*ptrs, wp, lp, n)
 
 
 def _elements(elements) -> np.ndarray:

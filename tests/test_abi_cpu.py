@@ -56,7 +56,7 @@ def _grid(nx=64, ny=64, dx=1e-4, dy=1e-4):
 
 @pytest.mark.parametrize("kw,code", [({"nx": 100}, -4), ({"ny": 512}, -4), ({"nx": 4}, -4),
                                      ({"dx": 0.0}, -1), ({"dy": -1e-4}, -1),
-                                     ({"dx": float("nan")}, -1), ({"nx": 256, "ny": 256}, -4)])
+                                     ({"dx": float("nan")}, -1), ({"nx": 512, "ny": 256}, -4)])
 def test_create_rejects_bad_grids_before_touching_the_device(lib, kw, code):
     h = ctypes.c_void_p(123)
     g = _grid(**kw)
@@ -75,7 +75,7 @@ def test_create_rejects_null_and_bad_precision(lib):
 
 def test_calls_on_null_context_are_einval(lib):
     from paper_2010_11540_amd.scpic import Particles
-    p = Particles(None, None, None, None, None, 0)
+    p = Particles(None, None, None, None, None, None, 0)
     e = np.zeros(1, dtype=[("kind", "<i4"), ("pad", "<i4"), ("p", "<f8", (16,))])
     assert lib.scpic_destroy(None) == 0
     assert lib.scpic_push(None, ctypes.byref(p), e.ctypes.data, 1) == -1

@@ -136,3 +136,45 @@ def test_two_particles_repel_antisymmetrically_with_inverse_distance(orc):
     # each particle carries half of the unit total charge
     assert abs(kx[1] - 0.5 / d) < 1e-3 * 0.5 / d
     assert abs(ky[0]) < 1e-9 * abs(kx[0])
+
+
+def test_weighted_kick_scales_the_unweighted_kick(orc):
+    """2.5D form: the kick of a particle with weight w_p is w_p times its
+    unweighted kick (same field, same interpolation)."""
+    g = inputs.make_grid(32)
+    p = inputs.gaussian_beam(2000, 51)
+    q, _ = orc.deposit(inputs.copy_parts(p), g)
+    ex, ey = orc.solve(q, 1.0 / ((1 << 24) * 2000), g)
+    a = inputs.copy_parts(p)
+    b = inputs.copy_parts(p)
+    b["w"] = np.random.default_rng(2).uniform(0.1, 1.0, 2000).astype(np.float32)
+    a["px"][:] = 0
+    a["py"][:] = 0
+    b["px"][:] = 0
+    b["py"][:] = 0
+    orc.kick(a, g, ex, ey, 1e-3)
+    orc.kick(b, g, ex, ey, 1e-3)
+    np.testing.assert_allclose(b["px"], a["px"] * b["w"].astype(np.float64), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(b["py"], a["py"] * b["w"].astype(np.float64), rtol=1e-15, atol=0)
+
+
+def test_line_density_weights_of_a_gaussian_bunch():
+    """Static 2.5D weights: lambda(z)/lambda_peak from a 128-bin histogram
+    follows the bunch's Gaussian profile exp(-z^2 / 2 sigma^2) (sigma = 0.25)
+    up to the histogram's counting noise: the least-squares scale between
+    weights and profile is 1 within the noise of the peak bin, and residuals
+    stay within a few counting errors."""
+    n, sigma = 400_000, 0.25
+    p = inputs.long_bunch_kv(n, 52)
+    w = p["w"].astype(np.float64)
+    z = p["z"]
+    assert p["w"].dtype == np.float32 and w.max() == 1.0 and w.min() > 0
+    assert np.all(np.abs(z) < 0.5)
+    core = np.abs(z) < 1.5 * sigma
+    prof = np.exp(-z[core] ** 2 / (2 * sigma ** 2))
+    c = np.dot(w[core], prof) / np.dot(prof, prof)
+    # peak bin holds ~ n * (1/128) / (sigma sqrt(2 pi)) counts -> ~1.2% noise
+    peak_count = n * (1.0 / 128) / (sigma * math.sqrt(2 * math.pi))
+    assert abs(c - 1.0) < 4 / math.sqrt(peak_count)
+    resid = np.abs(w[core] - c * prof)
+    assert resid.max() < 6 / math.sqrt(peak_count * prof.min()) + 0.02
