@@ -31,6 +31,7 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64  # read + write x, px, y, py in FP64
+BYTES_PER_WEIGHT = 4          # + the FP32 line-density kick weight (2.5D long bunch)
 PROFILE_TRAFFIC = ROOT / "profiles" / "pass_traffic_production.json"
 PASS_SOURCE = ROOT / "paper_2010_11540_amd" / "csrc" / "particles.hip"
 
@@ -38,9 +39,16 @@ PASS_SOURCE = ROOT / "paper_2010_11540_amd" / "csrc" / "particles.hip"
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed SC steps (multiple of steps/turn)")
-    ap.add_argument("--warmup", type=int, default=200, help="untimed SC steps before timing")
-    ap.add_argument("--workload", default="production", choices=["production", "small"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed SC steps, a multiple of the steps per turn (default: 1000 for "
+                         "production, 20 turns otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed SC steps before timing (default: 200 for production, 2 turns "
+                         "otherwise)")
+    ap.add_argument("--workload", default="production",
+                    choices=["production", "small", "large", "batch"],
+                    help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
+                         "bunch with line-density kick weights, 256^2; batch: 64-beam tune scan")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
     ap.add_argument("--pass-threads", type=int, default=0)
@@ -116,6 +124,120 @@ def cpu_baseline(w, seconds: float):
     }
 
 
+WORKLOAD_TEXT = {
+    "production": ("production 2D PIC: 1e6 Gaussian particles, 128x128 grid, per turn 100 4x4 "
+                   "maps + 10 thin sextupoles + 100 SC steps"),
+    "small": "small 2D PIC: 1e4 Gaussian particles, 64x64 grid, 16 SC steps/turn",
+    "large": ("large 2.5D PIC: 1e7 KV 2:1 long-bunch particles with 128-bin line-density kick "
+              "weights, 256x256 grid, 200 SC steps/turn"),
+    "batch": ("tune scan: 64 independent Gaussian beams of 1e4..5e5 particles (8.1e6 in all) on "
+              "64x64 / 128x128 grids, tunes on an 8x8 lattice in [4.05, 4.45]^2, 16 SC steps/turn"),
+}
+
+
+def default_steps(args, steps_per_turn: int):
+    if args.steps is None:
+        args.steps = 1000 if args.workload == "production" else 20 * steps_per_turn
+    if args.warmup is None:
+        args.warmup = 200 if args.workload == "production" else 2 * steps_per_turn
+
+
+def cpu_baseline_batch(w, seconds: float):
+    """The oracle on the host cores: each beam of the tune scan in turn through
+    its first 5 space-charge steps, until `seconds` of wall time."""
+    import numpy as np
+
+    import oracle
+    from paper_2010_11540_amd import inputs
+
+    oracle.lib()
+    done = 0
+    beams = 0
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        a, b = int(w["offsets"][k]), int(w["offsets"][k + 1])
+        lat = w["lattices"][k]
+        sc_idx = np.nonzero(lat["kind"] == inputs.SC)[0]
+        chunk = lat[: sc_idx[4] + 1]
+        parts = {key: v[a:b].copy() for key, v in w["parts"].items()}
+        oracle.track(parts, w["grids"][k], chunk, 1)
+        done += (b - a) * 5
+        beams += 1
+        k = (k + 1) % len(w["grids"])
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {
+        "value": done / el,
+        "unit": "particle-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"first 5 SC steps of {beams} beams of the tune scan (one after another), "
+                  f"{done} particle-steps, {el:.1f} s wall",
+    }
+
+
+def run_batch(args):
+    import torch
+
+    from paper_2010_11540_amd import inputs, scpic
+
+    w = inputs.batch_workload()
+    steps_per_turn = 16
+    default_steps(args, steps_per_turn)
+    if args.steps % steps_per_turn or args.warmup % steps_per_turn:
+        print(f"--steps and --warmup must be multiples of {steps_per_turn} (one turn)",
+              file=sys.stderr)
+        sys.exit(2)
+    b = scpic.Batch(w["grids"], w["offsets"], args.precision)
+    d = scpic.to_device(w["parts"])
+    torch.cuda.synchronize()
+    if args.warmup:
+        b.track(d, w["lattices"], args.warmup // steps_per_turn)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    b.track(d, w["lattices"], args.steps // steps_per_turn)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    print(f"[bench] timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
+          file=sys.stderr, flush=True)
+    n = w["n"]
+    alive = int((d["lost"] == 0).sum().item())
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline_batch(w, args.cpu_seconds)
+    out = {
+        "metric": "particle-steps/s (push+deposit+solve+kick)",
+        "value": n * args.steps / wall,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64 coords / f32 field",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["batch"], "particles": n, "beams": len(w["grids"]),
+                   "sc_steps_per_turn": steps_per_turn, "precision": args.precision,
+                   "graph": True, "alive_after": alive, "gpu_event_ms": round(gpu_ms, 3)},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    b.close()
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -135,9 +257,13 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.workload == "batch":
+        run_batch(args)
+        return
     w = inputs.workload(args.workload)
     lat = w["lattice"]
     steps_per_turn = int((lat["kind"] == inputs.SC).sum())
+    default_steps(args, steps_per_turn)
     if args.steps % steps_per_turn or args.warmup % steps_per_turn:
         print(f"--steps and --warmup must be multiples of {steps_per_turn} (one turn)",
               file=sys.stderr)
@@ -178,7 +304,7 @@ def main():
     # dominant kernel: the fused pass (kick + 4x4 map + deposit), timed alone
     # on the same stream over a copy of the beam
     d2 = {k: v.clone() for k, v in d.items()}
-    one_map = lat[lat["kind"] == inputs.LIN4X4][:1]
+    one_map = lat[lat["kind"] != inputs.SC][:1]
     kappa = float(lat["p"][lat["kind"] == inputs.SC][0, 0])
     scale = 1.0 / ((1 << 24) * n)
     for _ in range(5):
@@ -201,16 +327,19 @@ def main():
     g1.record(stream)
     torch.cuda.synchronize()
     grid_us = g0.elapsed_time(g1) * 1e3 / args.pass_reps
-    achieved = BYTES_PER_PARTICLE_STEP * n / (pass_us * 1e-6) / 1e9
+    unit_bytes = BYTES_PER_PARTICLE_STEP + (BYTES_PER_WEIGHT if "w" in d else 0)
+    achieved = unit_bytes * n / (pass_us * 1e-6) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": "k_pass<double,kick,deposit> (gather+kick, 4x4 map, CIC deposit, flush)",
+        "kernel": (f"k_pass<{'double' if args.precision == 'fp64' else 'float'},kick,deposit> "
+                   f"(gather+kick, {'4x4' if args.workload == 'production' else '2x2'} map, "
+                   "CIC deposit, flush)"),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(n),
-        "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE_STEP * n,
+        "algorithmic_bytes_per_launch": unit_bytes * n,
         "avg_launch_us": round(pass_us, 3),
         "grid_phase_us": round(grid_us, 3),
     }
@@ -235,10 +364,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 coords / f32 field",
         "data": "synthetic",
         "config": {
-            "workload": ("production 2D PIC: 1e6 Gaussian particles, 128x128 grid, per turn 100 "
-                         "4x4 maps + 10 thin sextupoles + 100 SC steps"
-                         if args.workload == "production" else
-                         "small 2D PIC: 1e4 Gaussian particles, 64x64 grid, 16 SC steps/turn"),
+            "workload": WORKLOAD_TEXT[args.workload],
             "particles": n,
             "grid": f"{w['grid']['nx']}x{w['grid']['ny']}",
             "sc_steps_per_turn": steps_per_turn,

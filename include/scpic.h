@@ -209,6 +209,52 @@ scpic_status scpic_reduce_solve(scpic_ctx *ctx, double scale);
  * scpic_reduce_solve) to ex, ey (device; double or float per precision). */
 scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey);
 
+/* ---- batches of independent beams --------------------------------------
+ * Many independent beams (a tune scan, Sec. V; beams of different sizes on
+ * different grids) tracked together: every particle pass and every grid
+ * phase is one launch over all beams, each beam keeping its own particles,
+ * grid, partials, field, ring and kick strengths.  Each beam's result is the
+ * one scpic_track gives for that beam alone. */
+typedef struct scpic_batch scpic_batch;
+
+/* Create a batch of n_inst beams (1 <= n_inst <= 4096).  Beam k owns the
+ * particles offsets[k] .. offsets[k+1]-1 of the concatenated arrays given to
+ * scpic_track_batched, and the grid grids[k] (the limits of scpic_create).
+ * offsets: host, n_inst + 1 entries, offsets[0] == 0, non-decreasing.
+ * grids: host, n_inst entries.  precision: as scpic_create.  hip_stream: the
+ * stream every call of the batch uses (NULL = default stream).  All
+ * workspaces are allocated here; beams with equal grids share the Green's
+ * spectrum and twiddle tables.  Errors: SCPIC_EINVAL (NULL or inconsistent
+ * arguments), SCPIC_EUNSUPPORTED (grid limits), SCPIC_ENOMEM, SCPIC_EHIP;
+ * *out is NULL on error. */
+scpic_status scpic_batch_create(scpic_batch **out, const scpic_grid *grids,
+                                const int64_t *offsets, int32_t n_inst, int32_t precision,
+                                void *hip_stream);
+
+/* Release a batch (waits for its stream).  NULL is accepted. */
+scpic_status scpic_batch_destroy(scpic_batch *b);
+
+/* Stream for the batch's later calls (NULL = default stream). */
+scpic_status scpic_batch_set_stream(scpic_batch *b, void *hip_stream);
+
+/* Track every beam n_turns turns through its own ring, as scpic_track does
+ * for one beam (same kick placement, same normalisation 1/(2^24 N0_k) with
+ * N0_k = offsets[k+1] - offsets[k], same lost-particle rules).
+ * parts: the concatenated beams (parts->n == offsets[n_inst]; w and lost
+ * may be NULL).  turns[k]: host array of n_els[k] elements, beam k's ring.
+ * The rings must share one schedule: the same number of SC elements, and in
+ * each stretch between consecutive SC elements (the stretch after the last
+ * SC element joined to the one before the first) at most 12 other elements;
+ * otherwise SCPIC_EUNSUPPORTED.  The step tables of a schedule are cached on
+ * the device (at most 16 schedules; one turn is one captured HIP graph). */
+scpic_status scpic_track_batched(scpic_batch *b, const scpic_particles *parts,
+                                 const scpic_element *const *turns, const int32_t *n_els,
+                                 int32_t n_turns);
+
+/* Copy beam k's node field after its last solve to ex, ey (device, nx*ny
+ * each, double or float per precision). */
+scpic_status scpic_batch_get_field(scpic_batch *b, int32_t k, void *ex, void *ey);
+
 #ifdef __cplusplus
 }
 #endif

@@ -204,10 +204,11 @@ __global__ void __launch_bounds__(kRowThreads)
 //   X[l] = (Z[l] + conj Z[ny-l]) / 2 - i W^l (Z[l] - conj Z[ny-l]) / 2,
 // W = exp(-2 pi i / my), for l = 0..ny.
 template <typename T, bool FROM_PARTIALS>
-__global__ void __launch_bounds__(kRowThreads)
-    k_rows_fwd(DepositTarget dep, int nblocks, const int64_t *__restrict__ q, double scale,
-               int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
-               cx<T> *__restrict__ at)
+__device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblocks,
+                                              const int64_t *__restrict__ q, double scale, int nx,
+                                              int ny, int my, int log2my,
+                                              const cx<T> *__restrict__ tw, cx<T> *__restrict__ at,
+                                              int i)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // my entries
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(kRowThreads)
     T *rho = reinterpret_cast<T *>(b + ny);             // ny
     __shared__ BlockHeader hdr[FROM_PARTIALS ? kMaxPassBlocks : 1];
     __shared__ unsigned long long red[FROM_PARTIALS ? kRowThreads * 4 : 1];
-    const int tid = threadIdx.x, i = blockIdx.x;
+    const int tid = threadIdx.x;
     // one round of loads: twiddles, and the headers or the dense row
     // (my <= 512 and nblocks <= 512 are below kRowThreads)
     const cx<T> tv = tid < my ? tw[tid] : cx<T>{T(0), T(0)};
@@ -249,13 +250,35 @@ __global__ void __launch_bounds__(kRowThreads)
     }
 }
 
+template <typename T, bool FROM_PARTIALS>
+__global__ void __launch_bounds__(kRowThreads)
+    k_rows_fwd(DepositTarget dep, int nblocks, const int64_t *__restrict__ q, double scale,
+               int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
+               cx<T> *__restrict__ at)
+{
+    rows_fwd_body<T, FROM_PARTIALS>(dep, nblocks, q, scale, nx, ny, my, log2my, tw, at,
+                                    (int)blockIdx.x);
+}
+
+// Every beam of a batch: workgroup -> (beam, row) from the batch's row table;
+// the rows come from the partials of the beam's last batched pass.
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_rows_fwd_batched(BatchLaunch b)
+{
+    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
+    rows_fwd_body<T, true>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny, I.my, I.log2_my,
+                           (const cx<T> *)I.tw_y, (cx<T> *)I.spec_a,
+                           (int)blockIdx.x - I.row_block0);
+}
+
 // Column l of the row spectra: forward FFT along x, times the Green's
 // spectrum, then the two differentiated inverse transforms, one per wave.
 template <typename T>
-__global__ void __launch_bounds__(kColThreads)
-    k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
-           const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
-           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by)
+__device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, int ny, int mx,
+                                          int log2mx, const cx<T> *__restrict__ tw,
+                                          const T *__restrict__ ghat_t, const T *__restrict__ sx,
+                                          const T *__restrict__ sy, cx<T> *__restrict__ bx,
+                                          cx<T> *__restrict__ by, int l)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
@@ -264,7 +287,6 @@ __global__ void __launch_bounds__(kColThreads)
     cx<T> *c = b + mx;
     cx<T> *d = c + mx;
     const int tid = threadIdx.x;
-    const int l = blockIdx.x;
     const cx<T> *col = at + (size_t)l * nx;
     const T *g = ghat_t + (size_t)l * mx;
     constexpr int kPer = kMaxFft / kColThreads;
@@ -312,21 +334,39 @@ __global__ void __launch_bounds__(kColThreads)
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kColThreads)
+    k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
+           const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
+           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by)
+{
+    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
+{
+    const BatchInstance &I = b.inst[b.col_inst[blockIdx.x]];
+    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
+                 (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
+                 (cx<T> *)I.spec_by, (int)blockIdx.x - I.col_block0);
+}
+
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
 // i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
 template <typename T>
-__global__ void __launch_bounds__(kInvThreads)
-    k_rows_inv(const cx<T> *__restrict__ bx, const cx<T> *__restrict__ by, int nx, int ny, int my,
-               int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
-               cx<T> *__restrict__ ef)
+__device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
+                                              const cx<T> *__restrict__ by, int nx, int ny, int my,
+                                              int log2my, const cx<T> *__restrict__ tw,
+                                              T *__restrict__ ex, T *__restrict__ ey,
+                                              cx<T> *__restrict__ ef, int i)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *a = twl + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
-    const int i = blockIdx.x;
     const cx<T> *rx = bx + (size_t)i * (ny + 1);
     const cx<T> *ry = by + (size_t)i * (ny + 1);
     constexpr int kPerT = kMaxFft / kInvThreads;          // twiddles per thread
@@ -371,6 +411,24 @@ __global__ void __launch_bounds__(kInvThreads)
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kInvThreads)
+    k_rows_inv(const cx<T> *__restrict__ bx, const cx<T> *__restrict__ by, int nx, int ny, int my,
+               int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
+               cx<T> *__restrict__ ef)
+{
+    rows_inv_body<T>(bx, by, nx, ny, my, log2my, tw, ex, ey, ef, (int)blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
+{
+    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
+    rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
+                     I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
+                     (int)blockIdx.x - I.row_block0);
+}
+
+template <typename T>
 hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *ey, void *ef)
 {
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)w.mx;
@@ -401,7 +459,32 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
     return launch_tail<T>(s, w, ex, ey, ef);
 }
 
+template <typename T>
+hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows, int cols,
+                                  int max_nx, int max_ny)
+{
+    const int mmx = 2 * max_nx, mmy = 2 * max_ny;
+    const size_t row_lds = sizeof(cx<T>) * (size_t)(mmy + 2 * max_ny) + sizeof(T) * (size_t)max_ny;
+    const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
+    const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)mmy;
+    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kRowThreads), row_lds, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cols_batched<T>, dim3(cols), dim3(kColThreads), col_lds, s, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rows_inv_batched<T>, dim3(rows), dim3(kInvThreads), inv_lds, s, b);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
+                                int cols, int max_nx, int max_ny)
+{
+    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny)
+                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny);
+}
 
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,
                          int64_t *q, int64_t *n_in)

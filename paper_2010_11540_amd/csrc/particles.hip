@@ -196,17 +196,21 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // beside the charge tile when it fits, and gathers from outside it read
 // global memory.  At the end each workgroup writes the bounding box of its
 // tile cells to its slice of the partials (no global atomics).
+// The body is shared by the single-beam kernel and the batched one: bid is
+// the workgroup's index among the nblk workgroups working on beam P (its
+// slice of the partials and its header), T = nblk * blockDim.x.
 template <typename TE, bool KICK, bool DEPOSIT>
-__global__ void __launch_bounds__(1024)
-    k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
-           PassElements els, DepositTarget dep, unsigned lds_bytes)
+__device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom &g,
+                                          const TE *__restrict__ ef, double kappa,
+                                          const PassElements &els, const DepositTarget &dep,
+                                          unsigned lds_bytes, int bid, int nblk)
 {
     using V = typename Vec2<TE>::type;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ int s_box[4];
     __shared__ int s_count;
-    const int64_t T = (int64_t)gridDim.x * blockDim.x;
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t T = (int64_t)nblk * blockDim.x;
+    int64_t p = (int64_t)bid * blockDim.x + threadIdx.x;
 
     // first particle's loads go out before the LDS set-up
     double x = 0, px = 0, y = 0, py = 0;
@@ -226,7 +230,7 @@ __global__ void __launch_bounds__(1024)
     hd.i1 = -2;
     hd.j0 = -1;
     hd.j1 = -2;
-    if (KICK || DEPOSIT) hd = dep.header[blockIdx.x];
+    if (KICK || DEPOSIT) hd = dep.header[bid];
     // LDS layout: [charge tile][staged field box + 2 nodes of slack]
     Box tile{0, 0, 0, 0};
     size_t tile_bytes = 0;
@@ -386,7 +390,7 @@ __global__ void __launch_bounds__(1024)
                 const int i = i0 + r, cc = c0 + (t - r * nch);
                 const uint4 v = *reinterpret_cast<const uint4 *>(lq + tile.at(i, 4 * cc));
                 reinterpret_cast<uint4 *>(dep.partial +
-                                          ((size_t)i * dep.max_blocks + blockIdx.x) * g.ny)[cc] = v;
+                                          ((size_t)i * dep.max_blocks + bid) * g.ny)[cc] = v;
             }
         }
         if (threadIdx.x == 0) {
@@ -397,9 +401,40 @@ __global__ void __launch_bounds__(1024)
             h.j1 = j1;
             h.count = s_count;
             h.pad[0] = h.pad[1] = h.pad[2] = 0;
-            dep.header[blockIdx.x] = h;
+            dep.header[bid] = h;
         }
     }
+}
+
+template <typename TE, bool KICK, bool DEPOSIT>
+__global__ void __launch_bounds__(1024)
+    k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
+           PassElements els, DepositTarget dep, unsigned lds_bytes)
+{
+    pass_body<TE, KICK, DEPOSIT>(P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x,
+                                 (int)gridDim.x);
+}
+
+// One pass over every beam of a batch: workgroup -> beam from the batch's
+// table, then the same body on that beam's particles, grid, field and
+// partials with its own kick strength and elements (steps[beam]).
+template <typename TE, bool KICK, bool DEPOSIT>
+__global__ void __launch_bounds__(1024)
+    k_pass_batched(BatchLaunch b, ParticlePtrs all, const BatchStep *__restrict__ steps,
+                   unsigned lds_bytes)
+{
+    const int k = b.pass_inst[blockIdx.x];
+    const BatchInstance &I = b.inst[k];
+    ParticlePtrs P;
+    P.x = all.x + I.p0;
+    P.px = all.px + I.p0;
+    P.y = all.y + I.p0;
+    P.py = all.py + I.p0;
+    P.w = all.w ? all.w + I.p0 : nullptr;
+    P.lost = all.lost ? all.lost + I.p0 : nullptr;
+    P.n = I.n;
+    pass_body<TE, KICK, DEPOSIT>(P, I.g, (const TE *)I.ef, steps[k].kappa, steps[k].els, I.dep,
+                                 lds_bytes, (int)blockIdx.x - I.pass_block0, I.pass_blocks);
 }
 
 // Between two node arrays (ex, ey) and the internal interleaved layout ef
@@ -433,6 +468,16 @@ hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g
     return hipGetLastError();
 }
 
+template <typename TE, bool KICK, bool DEPOSIT>
+hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
+                                 const BatchStep *steps, int blocks, int threads)
+{
+    const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
+    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), lds, s, b,
+                       all, steps, (unsigned)lds);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Allow the passes the dynamic LDS they use (beyond the default limit):
@@ -446,7 +491,13 @@ hipError_t prepare_pass_kernels(size_t lds_limit)
                            (const void *)k_pass<double, true, false>,
                            (const void *)k_pass<float, true, true>,
                            (const void *)k_pass<float, false, true>,
-                           (const void *)k_pass<float, true, false>};
+                           (const void *)k_pass<float, true, false>,
+                           (const void *)k_pass_batched<double, true, true>,
+                           (const void *)k_pass_batched<double, false, true>,
+                           (const void *)k_pass_batched<double, true, false>,
+                           (const void *)k_pass_batched<float, true, true>,
+                           (const void *)k_pass_batched<float, false, true>,
+                           (const void *)k_pass_batched<float, true, false>};
     for (const void *k : kerns) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_limit);
@@ -472,6 +523,21 @@ hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, 
                        : launch_pass_t<double, true, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
     return deposit ? launch_pass_t<double, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
                    : launch_pass_t<double, false, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
+}
+
+hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
+                               const BatchStep *steps, bool kick, bool mixed, bool deposit,
+                               int blocks, int threads)
+{
+    if (blocks <= 0) return hipSuccess;
+#define SCPIC_PB(T, K, D) launch_pass_batched_t<T, K, D>(s, b, all, steps, blocks, threads)
+    if (mixed) {
+        if (kick) return deposit ? SCPIC_PB(float, true, true) : SCPIC_PB(float, true, false);
+        return deposit ? SCPIC_PB(float, false, true) : SCPIC_PB(float, false, false);
+    }
+    if (kick) return deposit ? SCPIC_PB(double, true, true) : SCPIC_PB(double, true, false);
+    return deposit ? SCPIC_PB(double, false, true) : SCPIC_PB(double, false, false);
+#undef SCPIC_PB
 }
 
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,

@@ -117,6 +117,18 @@ scpic_status check_ctx(const scpic_ctx *c)
     return SCPIC_OK;
 }
 
+scpic_status check_grid(const scpic_grid *grid)
+{
+    if (!(grid->dx > 0.0) || !(grid->dy > 0.0) || !std::isfinite(grid->dx) ||
+        !std::isfinite(grid->dy) || !std::isfinite(grid->x_min) || !std::isfinite(grid->y_min))
+        return fail(SCPIC_EINVAL, "grid spacing must be positive and finite, origin finite");
+    if (!is_pow2_in(grid->nx, 8, 256) || !is_pow2_in(grid->ny, 8, 256))
+        return fail(SCPIC_EUNSUPPORTED, "nx and ny must be powers of two in [8, 256]");
+    if ((int64_t)grid->nx * grid->ny > kMaxCells)
+        return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 65536");
+    return SCPIC_OK;
+}
+
 scpic_status check_parts(const scpic_particles *p)
 {
     if (!p) return fail(SCPIC_EINVAL, "particles is NULL");
@@ -380,30 +392,40 @@ void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t)
 
 namespace {
 
+// Green's spectrum, twiddles and difference factors of a grid, converted to
+// T and copied to the given device tables.
 template <typename T>
-scpic_status upload_tables(scpic_ctx *c)
+scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x, void *tw_y,
+                                void *sx_t, void *sy_t)
 {
-    const int nx = c->grid.nx, ny = c->grid.ny, mx = 2 * nx, my = 2 * ny;
+    const int nx = grid.nx, ny = grid.ny, mx = 2 * nx, my = 2 * ny;
     std::vector<double> ghat((size_t)(ny + 1) * mx);
-    green_spectrum_host(nx, ny, c->grid.dx, c->grid.dy, ghat.data());
+    green_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
     std::vector<T> g_t(ghat.size()), twx(2 * (size_t)mx), twy(2 * (size_t)my), sx(mx), sy(ny + 1);
     for (size_t i = 0; i < ghat.size(); ++i) g_t[i] = (T)ghat[i];
     for (int t = 0; t < mx; ++t) {
         twx[2 * t] = (T)std::cos(2.0 * M_PI * t / mx);
         twx[2 * t + 1] = (T)(-std::sin(2.0 * M_PI * t / mx));
-        sx[t] = (T)(std::sin(2.0 * M_PI * t / mx) / c->grid.dx);
+        sx[t] = (T)(std::sin(2.0 * M_PI * t / mx) / grid.dx);
     }
     for (int t = 0; t < my; ++t) {
         twy[2 * t] = (T)std::cos(2.0 * M_PI * t / my);
         twy[2 * t + 1] = (T)(-std::sin(2.0 * M_PI * t / my));
     }
-    for (int l = 0; l <= ny; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / c->grid.dy);
-    SCPIC_HIP_TRY(hipMemcpy(c->sw.ghat_t, g_t.data(), sizeof(T) * g_t.size(), hipMemcpyHostToDevice), "upload ghat");
-    SCPIC_HIP_TRY(hipMemcpy(c->sw.tw_x, twx.data(), sizeof(T) * twx.size(), hipMemcpyHostToDevice), "upload twiddles");
-    SCPIC_HIP_TRY(hipMemcpy(c->sw.tw_y, twy.data(), sizeof(T) * twy.size(), hipMemcpyHostToDevice), "upload twiddles");
-    SCPIC_HIP_TRY(hipMemcpy(c->sw.sx, sx.data(), sizeof(T) * sx.size(), hipMemcpyHostToDevice), "upload sx");
-    SCPIC_HIP_TRY(hipMemcpy(c->sw.sy, sy.data(), sizeof(T) * sy.size(), hipMemcpyHostToDevice), "upload sy");
+    for (int l = 0; l <= ny; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / grid.dy);
+    SCPIC_HIP_TRY(hipMemcpy(ghat_t, g_t.data(), sizeof(T) * g_t.size(), hipMemcpyHostToDevice), "upload ghat");
+    SCPIC_HIP_TRY(hipMemcpy(tw_x, twx.data(), sizeof(T) * twx.size(), hipMemcpyHostToDevice), "upload twiddles");
+    SCPIC_HIP_TRY(hipMemcpy(tw_y, twy.data(), sizeof(T) * twy.size(), hipMemcpyHostToDevice), "upload twiddles");
+    SCPIC_HIP_TRY(hipMemcpy(sx_t, sx.data(), sizeof(T) * sx.size(), hipMemcpyHostToDevice), "upload sx");
+    SCPIC_HIP_TRY(hipMemcpy(sy_t, sy.data(), sizeof(T) * sy.size(), hipMemcpyHostToDevice), "upload sy");
     return SCPIC_OK;
+}
+
+template <typename T>
+scpic_status upload_tables(scpic_ctx *c)
+{
+    return upload_grid_tables<T>(c->grid, c->sw.ghat_t, c->sw.tw_x, c->sw.tw_y, c->sw.sx,
+                                 c->sw.sy);
 }
 
 scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision, void *stream)
@@ -485,13 +507,7 @@ scpic_status scpic_create(scpic_ctx **out, const scpic_grid *grid, int32_t preci
     if (!grid) return fail(SCPIC_EINVAL, "grid is NULL");
     if (precision != SCPIC_FP64 && precision != SCPIC_MIXED)
         return fail(SCPIC_EINVAL, "precision must be SCPIC_FP64 or SCPIC_MIXED");
-    if (!(grid->dx > 0.0) || !(grid->dy > 0.0) || !std::isfinite(grid->dx) ||
-        !std::isfinite(grid->dy) || !std::isfinite(grid->x_min) || !std::isfinite(grid->y_min))
-        return fail(SCPIC_EINVAL, "grid spacing must be positive and finite, origin finite");
-    if (!is_pow2_in(grid->nx, 8, 256) || !is_pow2_in(grid->ny, 8, 256))
-        return fail(SCPIC_EUNSUPPORTED, "nx and ny must be powers of two in [8, 256]");
-    if ((int64_t)grid->nx * grid->ny > kMaxCells)
-        return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 65536");
+    if (scpic_status st = check_grid(grid)) return st;
     scpic_ctx *c = new (std::nothrow) scpic_ctx();
     if (!c) return fail(SCPIC_ENOMEM, "host allocation failed");
     scpic_status st = create_impl(c, grid, precision, hip_stream);
@@ -686,6 +702,437 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
     std::vector<PassOp> tail;
     emit_segment(tail, true, last_kappa, trailing, false);
     return enqueue_ops(ctx, ctx->stream, parts, tail, scale);
+}
+
+}  // extern "C"
+
+// ---- batches of independent beams -----------------------------------------
+
+namespace {
+
+// Device step tables of one schedule (the op list shared by every beam) and,
+// for the steady turn, its captured graph.
+struct BatchSchedule {
+    std::vector<unsigned char> key;
+    std::vector<PassOp> shape;     // kick / deposit per op (kappa, els unused)
+    BatchStep *steps = nullptr;    // device [n_ops][n_inst]
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+constexpr size_t kMaxSchedules = 16;
+
+}  // namespace
+
+struct scpic_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    bool mixed = false;
+    int n_cu = 0;
+    int n_inst = 0;
+    int pass_threads = 1024;
+    std::vector<int64_t> offsets;
+    std::vector<scpic_grid> grids;
+    std::vector<BatchInstance> inst;  // host copy of the device table
+    BatchLaunch launch{};
+    int total_pass_blocks = 0, total_rows = 0, total_cols = 0, max_nx = 0, max_ny = 0;
+    std::vector<void *> allocations;
+    std::vector<BatchSchedule> schedules;
+    uint64_t use_counter = 0;
+};
+
+namespace {
+
+scpic_status batch_alloc(scpic_batch *b, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    b->allocations.push_back(*p);
+    return SCPIC_OK;
+}
+
+void batch_drop_schedule(BatchSchedule &s)
+{
+    if (s.exec) hipGraphExecDestroy(s.exec);
+    if (s.steps) hipFree(s.steps);
+    s.exec = nullptr;
+    s.steps = nullptr;
+}
+
+void batch_free_all(scpic_batch *b)
+{
+    for (auto &s : b->schedules) batch_drop_schedule(s);
+    b->schedules.clear();
+    for (void *p : b->allocations) hipFree(p);
+    b->allocations.clear();
+    if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+    b->capture_stream = nullptr;
+}
+
+// Workgroups of beam k in a batched pass: in proportion to its particles so
+// that the whole batch takes about one workgroup per compute unit, at least
+// one per non-empty beam, at most one per pass_threads particles.
+int batch_pass_blocks(int64_t n_k, int64_t total, int n_cu, int threads)
+{
+    if (n_k <= 0) return 0;
+    const int64_t share = (n_k * n_cu + total - 1) / total;
+    const int64_t need = (n_k + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({share, need, (int64_t)kMaxPassBlocks}));
+}
+
+struct GridTables {
+    scpic_grid grid;
+    void *ghat_t, *tw_x, *tw_y, *sx, *sy;
+};
+
+scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const int64_t *offsets,
+                               int n_inst, int32_t precision, void *stream)
+{
+    b->mixed = precision == SCPIC_MIXED;
+    b->stream = (hipStream_t)stream;
+    b->n_inst = n_inst;
+    b->offsets.assign(offsets, offsets + n_inst + 1);
+    b->grids.assign(grids, grids + n_inst);
+    SCPIC_HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    SCPIC_HIP_TRY(hipGetDeviceProperties(&prop, b->device), "hipGetDeviceProperties");
+    b->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    const size_t fe = b->mixed ? sizeof(float) : sizeof(double), ce = 2 * fe;
+    const int64_t total = offsets[n_inst];
+    std::vector<GridTables> tables;
+    std::vector<uint16_t> pass_inst, row_inst, col_inst;
+    b->inst.resize(n_inst);
+    scpic_status st;
+    void *p;
+#define BALLOC(dst, bytes)                                  \
+    do {                                                    \
+        if ((st = batch_alloc(b, &p, (bytes)))) return st;  \
+        dst = decltype(dst)(p);                             \
+    } while (0)
+    for (int k = 0; k < n_inst; ++k) {
+        const scpic_grid &gr = grids[k];
+        const int nx = gr.nx, ny = gr.ny, ncell = nx * ny;
+        const int64_t n_k = offsets[k + 1] - offsets[k];
+        BatchInstance &I = b->inst[k];
+        std::memset(&I, 0, sizeof(I));
+        I.p0 = offsets[k];
+        I.n = n_k;
+        I.pass_blocks = batch_pass_blocks(n_k, total, b->n_cu, b->pass_threads);
+        I.pass_block0 = b->total_pass_blocks;
+        b->total_pass_blocks += I.pass_blocks;
+        I.row_block0 = b->total_rows;
+        b->total_rows += nx;
+        I.col_block0 = b->total_cols;
+        b->total_cols += ny + 1;
+        b->max_nx = std::max(b->max_nx, nx);
+        b->max_ny = std::max(b->max_ny, ny);
+        for (int t = 0; t < I.pass_blocks; ++t) pass_inst.push_back((uint16_t)k);
+        for (int t = 0; t < nx; ++t) row_inst.push_back((uint16_t)k);
+        for (int t = 0; t <= ny; ++t) col_inst.push_back((uint16_t)k);
+        I.g.nx = nx;
+        I.g.ny = ny;
+        I.g.x_min = gr.x_min;
+        I.g.y_min = gr.y_min;
+        I.g.inv_dx = 1.0 / gr.dx;
+        I.g.inv_dy = 1.0 / gr.dy;
+        const int slices = std::max(1, I.pass_blocks);
+        BALLOC(I.dep.partial, sizeof(uint32_t) * (size_t)slices * ncell);
+        BALLOC(I.dep.header, sizeof(BlockHeader) * (size_t)slices);
+        BALLOC(I.dep.carry, sizeof(unsigned long long) * (size_t)ncell);
+        I.dep.max_blocks = slices;
+        I.nx = nx;
+        I.ny = ny;
+        I.mx = 2 * nx;
+        I.my = 2 * ny;
+        I.log2_mx = ilog2(2 * nx);
+        I.log2_my = ilog2(2 * ny);
+        I.scale = n_k > 0 ? 1.0 / (kChargeOne * (double)n_k) : 0.0;
+        const GridTables *gt = nullptr;
+        for (const GridTables &t : tables)
+            if (t.grid.nx == nx && t.grid.ny == ny && t.grid.dx == gr.dx && t.grid.dy == gr.dy)
+                gt = &t;
+        if (!gt) {
+            GridTables t;
+            t.grid = gr;
+            BALLOC(t.tw_x, ce * 2 * nx);
+            BALLOC(t.tw_y, ce * 2 * ny);
+            BALLOC(t.ghat_t, fe * (size_t)(ny + 1) * 2 * nx);
+            BALLOC(t.sx, fe * 2 * nx);
+            BALLOC(t.sy, fe * (ny + 1));
+            st = b->mixed ? upload_grid_tables<float>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy)
+                          : upload_grid_tables<double>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy);
+            if (st) return st;
+            tables.push_back(t);
+            gt = &tables.back();
+        }
+        I.tw_x = gt->tw_x;
+        I.tw_y = gt->tw_y;
+        I.ghat_t = gt->ghat_t;
+        I.sx = gt->sx;
+        I.sy = gt->sy;
+        BALLOC(I.spec_a, ce * (size_t)(ny + 1) * nx);
+        BALLOC(I.spec_bx, ce * (size_t)(ny + 1) * nx);
+        BALLOC(I.spec_by, ce * (size_t)(ny + 1) * nx);
+        BALLOC(I.ef, 2 * fe * ncell);
+        SCPIC_HIP_TRY(hipMemset(I.dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
+        SCPIC_HIP_TRY(hipMemset(I.dep.header, 0xff, sizeof(BlockHeader) * slices), "hipMemset");
+        SCPIC_HIP_TRY(hipMemset(I.ef, 0, 2 * fe * ncell), "hipMemset");
+    }
+    BatchInstance *inst_dev;
+    uint16_t *pass_dev, *row_dev, *col_dev;
+    BALLOC(inst_dev, sizeof(BatchInstance) * n_inst);
+    BALLOC(pass_dev, sizeof(uint16_t) * pass_inst.size());
+    BALLOC(row_dev, sizeof(uint16_t) * row_inst.size());
+    BALLOC(col_dev, sizeof(uint16_t) * col_inst.size());
+#undef BALLOC
+    SCPIC_HIP_TRY(hipMemcpy(inst_dev, b->inst.data(), sizeof(BatchInstance) * n_inst, hipMemcpyHostToDevice), "upload beams");
+    if (!pass_inst.empty())
+        SCPIC_HIP_TRY(hipMemcpy(pass_dev, pass_inst.data(), sizeof(uint16_t) * pass_inst.size(), hipMemcpyHostToDevice), "upload tables");
+    SCPIC_HIP_TRY(hipMemcpy(row_dev, row_inst.data(), sizeof(uint16_t) * row_inst.size(), hipMemcpyHostToDevice), "upload tables");
+    SCPIC_HIP_TRY(hipMemcpy(col_dev, col_inst.data(), sizeof(uint16_t) * col_inst.size(), hipMemcpyHostToDevice), "upload tables");
+    b->launch.inst = inst_dev;
+    b->launch.pass_inst = pass_dev;
+    b->launch.row_inst = row_dev;
+    b->launch.col_inst = col_dev;
+    b->launch.n_inst = n_inst;
+    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock - 256), "hipFuncSetAttribute");
+    SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    return SCPIC_OK;
+}
+
+bool same_shape(const std::vector<PassOp> &a, const std::vector<PassOp> &b)
+{
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+        if (a[i].kick != b[i].kick || a[i].deposit != b[i].deposit) return false;
+    return true;
+}
+
+// The cached schedule for per-beam op lists of one shape (ops[k] for beam k),
+// its step table uploaded on first use.
+scpic_status batch_schedule(scpic_batch *b, const std::vector<std::vector<PassOp>> &ops,
+                            const scpic_particles *parts, BatchSchedule **out)
+{
+    const size_t n_ops = ops[0].size(), n = (size_t)b->n_inst;
+    std::vector<BatchStep> table(n_ops * n);
+    for (size_t j = 0; j < n_ops; ++j)
+        for (size_t k = 0; k < n; ++k) {
+            BatchStep &t = table[j * n + k];
+            std::memset(&t, 0, sizeof(t));
+            t.kappa = ops[k][j].kappa;
+            t.els = ops[k][j].els;
+        }
+    std::vector<unsigned char> key;
+    auto put = [&key](const void *d, size_t len) {
+        const unsigned char *c = (const unsigned char *)d;
+        key.insert(key.end(), c, c + len);
+    };
+    put(parts, sizeof(*parts));
+    for (size_t j = 0; j < n_ops; ++j) {
+        put(&ops[0][j].kick, sizeof(bool));
+        put(&ops[0][j].deposit, sizeof(bool));
+    }
+    put(table.data(), sizeof(BatchStep) * table.size());
+    for (auto &s : b->schedules)
+        if (s.key == key) {
+            s.last_use = ++b->use_counter;
+            *out = &s;
+            return SCPIC_OK;
+        }
+    if (b->schedules.size() >= kMaxSchedules) {
+        // the evicted tables may still be read by queued work
+        SCPIC_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        auto it = std::min_element(b->schedules.begin(), b->schedules.end(),
+                                   [](const BatchSchedule &x, const BatchSchedule &y) {
+                                       return x.last_use < y.last_use;
+                                   });
+        batch_drop_schedule(*it);
+        b->schedules.erase(it);
+    }
+    BatchSchedule s;
+    s.key = std::move(key);
+    s.shape = ops[0];
+    hipError_t e = hipMalloc(&s.steps, sizeof(BatchStep) * std::max<size_t>(1, table.size()));
+    if (e != hipSuccess) return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    if (!table.empty()) {
+        e = hipMemcpy(s.steps, table.data(), sizeof(BatchStep) * table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(s.steps);
+            return fail_hip(e, "upload step table");
+        }
+    }
+    s.last_use = ++b->use_counter;
+    b->schedules.push_back(std::move(s));
+    *out = &b->schedules.back();
+    return SCPIC_OK;
+}
+
+scpic_status batch_enqueue(scpic_batch *b, hipStream_t s, const scpic_particles *parts,
+                           const BatchSchedule &sch)
+{
+    const ParticlePtrs all = to_ptrs(parts);
+    for (size_t j = 0; j < sch.shape.size(); ++j) {
+        const PassOp &op = sch.shape[j];
+        hipError_t e = launch_pass_batched(s, b->launch, all, sch.steps + j * b->n_inst, op.kick,
+                                           b->mixed, op.deposit, b->total_pass_blocks,
+                                           b->pass_threads);
+        if (e != hipSuccess) return fail_hip(e, "batched pass launch");
+        if (op.deposit) {
+            e = launch_solve_batched(s, b->launch, b->mixed, b->total_rows, b->total_cols,
+                                     b->max_nx, b->max_ny);
+            if (e != hipSuccess) return fail_hip(e, "batched solve launch");
+        }
+    }
+    return SCPIC_OK;
+}
+
+scpic_status batch_graph(scpic_batch *b, const scpic_particles *parts, BatchSchedule &sch)
+{
+    if (sch.exec) return SCPIC_OK;
+    if (!b->capture_stream)
+        SCPIC_HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    SCPIC_HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal),
+                  "hipStreamBeginCapture");
+    scpic_status st = batch_enqueue(b, b->capture_stream, parts, sch);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->capture_stream, &graph);
+    if (st) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&sch.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        sch.exec = nullptr;
+        return fail_hip(e, "hipGraphInstantiate");
+    }
+    return SCPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scpic_status scpic_batch_create(scpic_batch **out, const scpic_grid *grids,
+                                const int64_t *offsets, int32_t n_inst, int32_t precision,
+                                void *hip_stream)
+{
+    g_last_error.clear();
+    if (!out) return fail(SCPIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grids || !offsets) return fail(SCPIC_EINVAL, "grids and offsets must be non-NULL");
+    if (n_inst < 1 || n_inst > 4096) return fail(SCPIC_EINVAL, "n_inst must be in [1, 4096]");
+    if (precision != SCPIC_FP64 && precision != SCPIC_MIXED)
+        return fail(SCPIC_EINVAL, "precision must be SCPIC_FP64 or SCPIC_MIXED");
+    if (offsets[0] != 0) return fail(SCPIC_EINVAL, "offsets[0] must be 0");
+    for (int k = 0; k < n_inst; ++k) {
+        if (offsets[k + 1] < offsets[k])
+            return fail(SCPIC_EINVAL, "offsets must not decrease (at beam " + std::to_string(k) + ")");
+        if (scpic_status st = check_grid(&grids[k])) {
+            g_last_error = "beam " + std::to_string(k) + ": " + g_last_error;
+            return st;
+        }
+    }
+    scpic_batch *b = new (std::nothrow) scpic_batch();
+    if (!b) return fail(SCPIC_ENOMEM, "host allocation failed");
+    scpic_status st = batch_create_impl(b, grids, offsets, n_inst, precision, hip_stream);
+    if (st) {
+        batch_free_all(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_batch_destroy(scpic_batch *b)
+{
+    g_last_error.clear();
+    if (!b) return SCPIC_OK;
+    hipStreamSynchronize(b->stream);
+    batch_free_all(b);
+    delete b;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_batch_set_stream(scpic_batch *b, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!b) return fail(SCPIC_EINVAL, "batch is NULL");
+    b->stream = (hipStream_t)hip_stream;
+    return SCPIC_OK;
+}
+
+scpic_status scpic_track_batched(scpic_batch *b, const scpic_particles *parts,
+                                 const scpic_element *const *turns, const int32_t *n_els,
+                                 int32_t n_turns)
+{
+    g_last_error.clear();
+    if (!b) return fail(SCPIC_EINVAL, "batch is NULL");
+    if (scpic_status st = check_parts(parts)) return st;
+    if (parts->n != b->offsets.back())
+        return fail(SCPIC_EINVAL, "parts->n must equal offsets[n_inst] of the batch");
+    if (!turns || !n_els) return fail(SCPIC_EINVAL, "turns and n_els must be non-NULL");
+    if (n_turns < 0) return fail(SCPIC_EINVAL, "n_turns is negative");
+    const int n = b->n_inst;
+    std::vector<std::vector<PassOp>> first(n), steady(n), tail(n);
+    bool any_sc0 = false;
+    for (int k = 0; k < n; ++k) {
+        std::vector<const scpic_element *> all, trailing;
+        if (scpic_status st = collect_elements(turns[k], n_els[k], all, true)) {
+            g_last_error = "beam " + std::to_string(k) + ": " + g_last_error;
+            return st;
+        }
+        bool any_sc = false;
+        double last_kappa = 0.0;
+        build_turn(all, true, first[k], any_sc, last_kappa, trailing);
+        if (any_sc) {
+            build_turn(all, false, steady[k], any_sc, last_kappa, trailing);
+            emit_segment(tail[k], true, last_kappa, trailing, false);
+        }
+        if (k == 0) any_sc0 = any_sc;
+        if (any_sc != any_sc0 || !same_shape(first[k], first[0]) ||
+            !same_shape(steady[k], steady[0]) || !same_shape(tail[k], tail[0]))
+            return fail(SCPIC_EUNSUPPORTED,
+                        "beam " + std::to_string(k) +
+                            ": its ring does not share the schedule of beam 0 (same number of "
+                            "SC elements, at most 12 other elements between them)");
+    }
+    if (n_turns == 0 || parts->n == 0) return SCPIC_OK;
+    BatchSchedule *sch = nullptr;
+    if (!any_sc0) {
+        if (scpic_status st = batch_schedule(b, first, parts, &sch)) return st;
+        for (int t = 0; t < n_turns; ++t)
+            if (scpic_status st = batch_enqueue(b, b->stream, parts, *sch)) return st;
+        return SCPIC_OK;
+    }
+    if (scpic_status st = batch_schedule(b, first, parts, &sch)) return st;
+    if (scpic_status st = batch_enqueue(b, b->stream, parts, *sch)) return st;
+    if (n_turns > 1) {
+        if (scpic_status st = batch_schedule(b, steady, parts, &sch)) return st;
+        if (scpic_status st = batch_graph(b, parts, *sch)) return st;
+        for (int t = 1; t < n_turns; ++t)
+            SCPIC_HIP_TRY(hipGraphLaunch(sch->exec, b->stream), "hipGraphLaunch");
+    }
+    if (scpic_status st = batch_schedule(b, tail, parts, &sch)) return st;
+    return batch_enqueue(b, b->stream, parts, *sch);
+}
+
+scpic_status scpic_batch_get_field(scpic_batch *b, int32_t k, void *ex, void *ey)
+{
+    g_last_error.clear();
+    if (!b) return fail(SCPIC_EINVAL, "batch is NULL");
+    if (k < 0 || k >= b->n_inst) return fail(SCPIC_EINVAL, "beam index out of range");
+    if (!ex || !ey) return fail(SCPIC_EINVAL, "ex and ey must be non-NULL");
+    const BatchInstance &I = b->inst[k];
+    hipError_t e = launch_interleave(b->stream, b->mixed, false, ex, ey, I.ef, I.nx * I.ny);
+    if (e != hipSuccess) return fail_hip(e, "field copy launch");
+    return SCPIC_OK;
 }
 
 }  // extern "C"

@@ -67,6 +67,39 @@ struct ParticlePtrs {
     int64_t n;
 };
 
+// One beam of a batch, as the batched kernels see it: its particles (a
+// contiguous range of the concatenated arrays), its grid, its partials and
+// its solve workspace, and where its workgroups start in each batched launch.
+struct BatchInstance {
+    int64_t p0, n;                     // particles [p0, p0 + n)
+    int32_t pass_block0, pass_blocks;  // its workgroups in a batched pass
+    int32_t row_block0, col_block0;    // its first workgroup in the row / column kernels
+    GridGeom g;
+    DepositTarget dep;                 // max_blocks == pass_blocks
+    int32_t nx, ny, mx, my, log2_mx, log2_my;
+    double scale;                      // 1 / (2^24 N0): charge units -> rho
+    const void *tw_x, *tw_y, *ghat_t, *sx, *sy;
+    void *spec_a, *spec_bx, *spec_by;
+    void *ef;                          // interleaved node field
+};
+
+// What one batched pass applies to one beam: its pending kick strength and
+// the elements up to its next space-charge location.
+struct BatchStep {
+    double kappa;
+    PassElements els;
+};
+
+// Device tables of a batch: the beams and, per batched launch, the beam of
+// each workgroup.
+struct BatchLaunch {
+    const BatchInstance *inst;
+    const uint16_t *pass_inst;  // [total pass workgroups]
+    const uint16_t *row_inst;   // [sum nx]: row-forward and row-inverse kernels
+    const uint16_t *col_inst;   // [sum (ny + 1)]: column kernel
+    int32_t n_inst;
+};
+
 // ---- launchers (particles.hip) ------------------------------------------
 // ef: interleaved node field (Ex, Ey per node), double or float per mixed.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
@@ -78,6 +111,12 @@ hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, voi
                              void *ef, int ncell);
 
 hipError_t prepare_pass_kernels(size_t lds_bytes);
+
+// One particle pass over every beam of a batch (blocks = total pass
+// workgroups of the batch); steps[beam] holds each beam's kick and elements.
+hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
+                               const BatchStep *steps, bool kick, bool mixed, bool deposit,
+                               int blocks, int threads);
 
 // Exact charge grid q (int64) and deposited count from the partials of the
 // last depositing pass (blocks_used workgroups); clears the carry grid.
@@ -104,6 +143,11 @@ hipError_t launch_solve(hipStream_t s, const SolveWorkspace &w, const int64_t *q
 // integer reduction is fused into the first FFT stage), interleaved into ef.
 hipError_t launch_solve_partials(hipStream_t s, const SolveWorkspace &w, const DepositTarget &dep,
                                  int blocks_used, double scale, void *ef);
+
+// Field of every beam of a batch from the partials of its last batched pass,
+// interleaved into each beam's ef: rows = sum of nx, cols = sum of (ny + 1).
+hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
+                                int cols, int max_nx, int max_ny);
 
 // Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
 // the padded 2nx x 2ny periodic kernel.

@@ -267,5 +267,49 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
             "turns": turns, "n": n, "seed": seed}
 
 
+def concat_parts(beams: list[dict]) -> tuple[dict, np.ndarray]:
+    """Concatenate per-beam particle dicts (same keys) and return the CSR
+    offsets of the beams."""
+    keys = beams[0].keys()
+    parts = {k: np.ascontiguousarray(np.concatenate([b[k] for b in beams])) for k in keys}
+    offsets = np.zeros(len(beams) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([b["x"].shape[0] for b in beams])
+    return parts, offsets
+
+
+def batch_workload(n_inst: int = 64, seed: int | None = None, n_min: float = 1e4,
+                   n_max: float = 5e5, turns: int = 200, tune_lo: float = 4.05,
+                   tune_hi: float = 4.45) -> dict:
+    """A tune scan as one batch of independent beams (the paper's Sec. V scans
+    tunes beam by beam).
+
+    Beam k: N_k = round(10^U(log10 n_min, log10 n_max)) Gaussian particles
+    (the same distribution as the other workloads, its own seed), on a 64^2
+    grid over +-6 sigma when N_k < 1e5, else 128^2; its ring is the small
+    workload's (16 segments of 2x2 maps, one SC kick each, kappa for
+    dnu = -0.2) at the tunes (Q_x, Q_y) of point k of an s x s lattice over
+    [tune_lo, tune_hi]^2 (s = ceil(sqrt(n_inst))).  Beams near the integer lose
+    particles, which exercises the lost flags and uneven beam sizes."""
+    seed = SEED_BASE + 4 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(math.log10(n_min), math.log10(n_max), size=n_inst)
+    sizes = np.rint(10.0 ** u).astype(np.int64)
+    side = int(math.ceil(math.sqrt(n_inst)))
+    q = np.linspace(tune_lo, tune_hi, side)
+    eps = 1e-6
+    kappa = kappa_for_tune_shift(-0.2, eps, 16)
+    beams, grids, lattices, tunes = [], [], [], []
+    for k in range(n_inst):
+        qx, qy = q[k % side], q[(k // side) % side]
+        beams.append(gaussian_beam(int(sizes[k]), seed * 1000 + k))
+        grids.append(make_grid(64 if sizes[k] < 100_000 else 128))
+        lattices.append(ring(qx, qy, 16, kappa))
+        tunes.append((qx, qy))
+    parts, offsets = concat_parts(beams)
+    return {"name": "batch", "parts": parts, "offsets": offsets, "grids": grids,
+            "lattices": lattices, "tunes": tunes, "sizes": sizes, "turns": turns,
+            "n": int(offsets[-1]), "seed": seed}
+
+
 def copy_parts(parts: dict) -> dict:
     return {k: v.copy() for k, v in parts.items()}

@@ -29,7 +29,8 @@ OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS = 1, 2, 3
 EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_set_stream", "scpic_push", "scpic_deposit", "scpic_solve", "scpic_kick",
            "scpic_track", "scpic_set_option", "scpic_pass", "scpic_reduce_solve",
-           "scpic_get_field")
+           "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
+           "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_get_field")
 
 
 class Grid(ctypes.Structure):
@@ -76,6 +77,13 @@ def load_library(path: Path | str | None = None):
     L.scpic_pass.argtypes = [vp, ctypes.POINTER(Particles), i32, dbl, vp, i32, i32]
     L.scpic_reduce_solve.argtypes = [vp, dbl]
     L.scpic_get_field.argtypes = [vp, vp, vp]
+    L.scpic_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid),
+                                     ctypes.POINTER(i64), i32, i32, vp]
+    L.scpic_batch_destroy.argtypes = [vp]
+    L.scpic_batch_set_stream.argtypes = [vp, vp]
+    L.scpic_track_batched.argtypes = [vp, ctypes.POINTER(Particles), ctypes.POINTER(vp),
+                                      ctypes.POINTER(i32), i32]
+    L.scpic_batch_get_field.argtypes = [vp, i32, vp, vp]
     for name in EXPORTS:
         if name not in ("scpic_version", "scpic_last_error"):
             getattr(L, name).restype = i32
@@ -250,4 +258,74 @@ class Context:
         ex = torch.empty(self.ncell, dtype=self.field_dtype, device=dev)
         ey = torch.empty_like(ex)
         _check(self._lib.scpic_get_field(self._h, ex.data_ptr(), ey.data_ptr()))
+        return ex, ey
+
+
+def _grid_struct(grid: dict) -> Grid:
+    return Grid(int(grid["nx"]), int(grid["ny"]), float(grid["x_min"]), float(grid["y_min"]),
+                float(grid["dx"]), float(grid["dy"]))
+
+
+class Batch:
+    """Independent beams tracked together: beam k owns particles
+    offsets[k]:offsets[k+1] of the concatenated arrays and the grid grids[k]."""
+
+    def __init__(self, grids, offsets, precision: str = "fp64", stream=None):
+        L = load_library()
+        self._lib = L
+        self.grids = [dict(g) for g in grids]
+        n = len(self.grids)
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        if self.offsets.shape != (n + 1,):
+            raise ValueError(f"offsets must have {n + 1} entries")
+        self.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        self.field_dtype = torch.float64 if self.precision == FP64 else torch.float32
+        garr = (Grid * n)(*[_grid_struct(g) for g in self.grids])
+        h = ctypes.c_void_p()
+        _check(L.scpic_batch_create(ctypes.byref(h), garr,
+                                    self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    n, self.precision, _stream_ptr(stream)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.scpic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _sync_stream(self, stream=None):
+        _check(self._lib.scpic_batch_set_stream(self._h, _stream_ptr(stream)))
+
+    def track(self, parts: dict, lattices, n_turns: int, stream=None):
+        """Track every beam n_turns turns; lattices[k] is beam k's one-turn ring."""
+        self._sync_stream(stream)
+        els = [_elements(lat) for lat in lattices]
+        if len(els) != len(self.grids):
+            raise ValueError(f"need {len(self.grids)} lattices, got {len(els)}")
+        ptrs = (ctypes.c_void_p * len(els))(*[e.ctypes.data for e in els])
+        counts = np.array([len(e) for e in els], dtype=np.int32)
+        p = particles_struct(parts)
+        _check(self._lib.scpic_track_batched(
+            self._h, ctypes.byref(p), ptrs,
+            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_turns)))
+
+    def get_field(self, k: int, stream=None):
+        self._sync_stream(stream)
+        g = self.grids[k]
+        ncell = int(g["nx"]) * int(g["ny"])
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ex = torch.empty(ncell, dtype=self.field_dtype, device=dev)
+        ey = torch.empty_like(ex)
+        _check(self._lib.scpic_batch_get_field(self._h, int(k), ex.data_ptr(), ey.data_ptr()))
         return ex, ey

@@ -89,3 +89,35 @@ def test_calls_on_null_context_are_einval(lib):
     assert lib.scpic_reduce_solve(None, 1.0) == -1
     assert lib.scpic_get_field(None, None, None) == -1
     assert b"ctx" in lib.scpic_last_error()
+
+
+def test_batch_create_rejects_bad_arguments_before_touching_the_device(lib):
+    from paper_2010_11540_amd.scpic import Grid
+    h = ctypes.c_void_p(123)
+    good = (Grid * 2)(_grid(), _grid(32, 32))
+    bad_grid = (Grid * 2)(_grid(), _grid(nx=100))
+    off = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    cases = [
+        (good, off(0, 10, 20), 0, 0, -1),     # n_inst 0
+        (good, off(1, 10, 20), 2, 0, -1),     # offsets[0] != 0
+        (good, off(0, 10, 5), 2, 0, -1),      # decreasing
+        (good, off(0, 10, 20), 2, 5, -1),     # precision
+        (bad_grid, off(0, 10, 20), 2, 0, -4),  # grid limits
+    ]
+    for grids, offs, n, prec, code in cases:
+        assert lib.scpic_batch_create(ctypes.byref(h), grids, offs, n, prec, None) == code
+        assert h.value is None
+        assert lib.scpic_last_error()
+    assert lib.scpic_batch_create(None, good, off(0, 1, 2), 2, 0, None) == -1
+    assert lib.scpic_batch_create(ctypes.byref(h), None, off(0, 1, 2), 2, 0, None) == -1
+    assert lib.scpic_batch_create(ctypes.byref(h), good, None, 2, 0, None) == -1
+
+
+def test_batch_calls_on_null_batch_are_einval(lib):
+    from paper_2010_11540_amd.scpic import Particles
+    p = Particles(None, None, None, None, None, None, 0)
+    assert lib.scpic_batch_destroy(None) == 0
+    assert lib.scpic_batch_set_stream(None, None) == -1
+    assert lib.scpic_track_batched(None, ctypes.byref(p), None, None, 1) == -1
+    assert lib.scpic_batch_get_field(None, 0, None, None) == -1
+    assert b"batch" in lib.scpic_last_error()
