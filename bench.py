@@ -193,6 +193,9 @@ def run_batch(args):
     b = scpic.Batch(w["grids"], w["offsets"], args.precision)
     d = scpic.to_device(w["parts"])
     torch.cuda.synchronize()
+    threads, per_cu = b.autotune(d, w["lattices"], trial_turns=2)
+    print(f"[bench] autotuned pass shape: {threads} threads, {per_cu} workgroups per CU",
+          file=sys.stderr, flush=True)
     if args.warmup:
         b.track(d, w["lattices"], args.warmup // steps_per_turn)
     torch.cuda.synchronize()
@@ -230,7 +233,8 @@ def run_batch(args):
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["batch"], "particles": n, "beams": len(w["grids"]),
                    "sc_steps_per_turn": steps_per_turn, "precision": args.precision,
-                   "graph": True, "alive_after": alive, "gpu_event_ms": round(gpu_ms, 3)},
+                   "graph": True, "pass_threads": threads, "pass_workgroups_per_cu": per_cu,
+                   "alive_after": alive, "gpu_event_ms": round(gpu_ms, 3)},
         "roofline": None,
         "cpu_baseline": cpu,
     }

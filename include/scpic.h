@@ -251,6 +251,21 @@ scpic_status scpic_track_batched(scpic_batch *b, const scpic_particles *parts,
                                  const scpic_element *const *turns, const int32_t *n_els,
                                  int32_t n_turns);
 
+/* Pick the launch shape of the batched particle pass by timing it: for each
+ * candidate (threads per workgroup 256, 512 or 1024; workgroups per compute
+ * unit over the whole batch 1, 2 or 4, which sets the particles per
+ * workgroup and the number of LDS charge-grid copies and partial slices of
+ * each beam) one untimed and trial_turns timed turns run on a device scratch
+ * copy of parts (allocated and freed here; parts itself is not modified),
+ * and the fastest candidate is kept for later scpic_track_batched calls.
+ * Results do not depend on the shape.  threads_out, blocks_per_cu_out (host,
+ * may be NULL) receive the choice.  trial_turns in [1, 100].  Drops the
+ * batch's cached schedules; waits for the batch's stream. */
+scpic_status scpic_batch_autotune(scpic_batch *b, const scpic_particles *parts,
+                                  const scpic_element *const *turns, const int32_t *n_els,
+                                  int32_t trial_turns, int32_t *threads_out,
+                                  int32_t *blocks_per_cu_out);
+
 /* Copy beam k's node field after its last solve to ex, ey (device, nx*ny
  * each, double or float per precision). */
 scpic_status scpic_batch_get_field(scpic_batch *b, int32_t k, void *ex, void *ey);

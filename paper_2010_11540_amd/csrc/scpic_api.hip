@@ -731,8 +731,11 @@ struct scpic_batch {
     bool mixed = false;
     int n_cu = 0;
     int n_inst = 0;
-    int pass_threads = 1024;
+    int pass_threads = 1024;  // launch shape of the batched pass (autotuned)
+    int blocks_per_cu = 1;
     std::vector<int64_t> offsets;
+    std::vector<int> max_slices;      // partial slices allocated per beam
+    uint16_t *pass_table = nullptr;   // device, sized for the largest shape
     std::vector<scpic_grid> grids;
     std::vector<BatchInstance> inst;  // host copy of the device table
     BatchLaunch launch{};
@@ -774,14 +777,48 @@ void batch_free_all(scpic_batch *b)
 }
 
 // Workgroups of beam k in a batched pass: in proportion to its particles so
-// that the whole batch takes about one workgroup per compute unit, at least
-// one per non-empty beam, at most one per pass_threads particles.
-int batch_pass_blocks(int64_t n_k, int64_t total, int n_cu, int threads)
+// that the whole batch takes about `slots` workgroups (blocks_per_cu per
+// compute unit), at least one per non-empty beam, at most one per `threads`
+// particles.
+int batch_pass_blocks(int64_t n_k, int64_t total, int64_t slots, int threads)
 {
     if (n_k <= 0) return 0;
-    const int64_t share = (n_k * n_cu + total - 1) / total;
+    const int64_t share = (n_k * slots + total - 1) / total;
     const int64_t need = (n_k + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>({share, need, (int64_t)kMaxPassBlocks}));
+}
+
+// Candidate launch shapes of the batched pass (threads per workgroup,
+// workgroups per compute unit); the largest allocation covers them all.
+constexpr int kTuneThreads[] = {256, 512, 1024};
+constexpr int kTuneBlocksPerCu[] = {1, 2, 4};
+constexpr int kMinTuneThreads = 256, kMaxTuneBlocksPerCu = 4;
+
+// Lay the batched pass out for a launch shape: each beam's workgroups and the
+// workgroup -> beam table, uploaded with the beam table.  Headers restart as
+// "unknown" (their boxes belonged to the previous assignment of particles).
+scpic_status batch_layout(scpic_batch *b, int threads, int blocks_per_cu)
+{
+    const int64_t total = b->offsets.back();
+    std::vector<uint16_t> pass_inst;
+    b->total_pass_blocks = 0;
+    for (int k = 0; k < b->n_inst; ++k) {
+        BatchInstance &I = b->inst[k];
+        I.pass_blocks = std::min(
+            b->max_slices[k],
+            batch_pass_blocks(I.n, total, (int64_t)b->n_cu * blocks_per_cu, threads));
+        I.pass_block0 = b->total_pass_blocks;
+        b->total_pass_blocks += I.pass_blocks;
+        for (int t = 0; t < I.pass_blocks; ++t) pass_inst.push_back((uint16_t)k);
+        SCPIC_HIP_TRY(hipMemsetAsync(I.dep.header, 0xff, sizeof(BlockHeader) * I.dep.max_blocks, b->stream), "hipMemsetAsync");
+    }
+    b->pass_threads = threads;
+    b->blocks_per_cu = blocks_per_cu;
+    SCPIC_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    SCPIC_HIP_TRY(hipMemcpy((void *)b->launch.inst, b->inst.data(), sizeof(BatchInstance) * b->n_inst, hipMemcpyHostToDevice), "upload beams");
+    if (!pass_inst.empty())
+        SCPIC_HIP_TRY(hipMemcpy(b->pass_table, pass_inst.data(), sizeof(uint16_t) * pass_inst.size(), hipMemcpyHostToDevice), "upload tables");
+    return SCPIC_OK;
 }
 
 struct GridTables {
@@ -804,8 +841,10 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
     const size_t fe = b->mixed ? sizeof(float) : sizeof(double), ce = 2 * fe;
     const int64_t total = offsets[n_inst];
     std::vector<GridTables> tables;
-    std::vector<uint16_t> pass_inst, row_inst, col_inst;
+    std::vector<uint16_t> row_inst, col_inst;
+    size_t pass_table_len = 0;
     b->inst.resize(n_inst);
+    b->max_slices.resize(n_inst);
     scpic_status st;
     void *p;
 #define BALLOC(dst, bytes)                                  \
@@ -821,16 +860,16 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         std::memset(&I, 0, sizeof(I));
         I.p0 = offsets[k];
         I.n = n_k;
-        I.pass_blocks = batch_pass_blocks(n_k, total, b->n_cu, b->pass_threads);
-        I.pass_block0 = b->total_pass_blocks;
-        b->total_pass_blocks += I.pass_blocks;
+        // enough partial slices for every candidate launch shape
+        b->max_slices[k] = std::max(
+            1, batch_pass_blocks(n_k, total, (int64_t)b->n_cu * kMaxTuneBlocksPerCu, kMinTuneThreads));
+        pass_table_len += (size_t)b->max_slices[k];
         I.row_block0 = b->total_rows;
         b->total_rows += nx;
         I.col_block0 = b->total_cols;
         b->total_cols += ny + 1;
         b->max_nx = std::max(b->max_nx, nx);
         b->max_ny = std::max(b->max_ny, ny);
-        for (int t = 0; t < I.pass_blocks; ++t) pass_inst.push_back((uint16_t)k);
         for (int t = 0; t < nx; ++t) row_inst.push_back((uint16_t)k);
         for (int t = 0; t <= ny; ++t) col_inst.push_back((uint16_t)k);
         I.g.nx = nx;
@@ -839,7 +878,7 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         I.g.y_min = gr.y_min;
         I.g.inv_dx = 1.0 / gr.dx;
         I.g.inv_dy = 1.0 / gr.dy;
-        const int slices = std::max(1, I.pass_blocks);
+        const int slices = b->max_slices[k];
         BALLOC(I.dep.partial, sizeof(uint32_t) * (size_t)slices * ncell);
         BALLOC(I.dep.header, sizeof(BlockHeader) * (size_t)slices);
         BALLOC(I.dep.carry, sizeof(unsigned long long) * (size_t)ncell);
@@ -885,13 +924,10 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
     BatchInstance *inst_dev;
     uint16_t *pass_dev, *row_dev, *col_dev;
     BALLOC(inst_dev, sizeof(BatchInstance) * n_inst);
-    BALLOC(pass_dev, sizeof(uint16_t) * pass_inst.size());
+    BALLOC(pass_dev, sizeof(uint16_t) * pass_table_len);
     BALLOC(row_dev, sizeof(uint16_t) * row_inst.size());
     BALLOC(col_dev, sizeof(uint16_t) * col_inst.size());
 #undef BALLOC
-    SCPIC_HIP_TRY(hipMemcpy(inst_dev, b->inst.data(), sizeof(BatchInstance) * n_inst, hipMemcpyHostToDevice), "upload beams");
-    if (!pass_inst.empty())
-        SCPIC_HIP_TRY(hipMemcpy(pass_dev, pass_inst.data(), sizeof(uint16_t) * pass_inst.size(), hipMemcpyHostToDevice), "upload tables");
     SCPIC_HIP_TRY(hipMemcpy(row_dev, row_inst.data(), sizeof(uint16_t) * row_inst.size(), hipMemcpyHostToDevice), "upload tables");
     SCPIC_HIP_TRY(hipMemcpy(col_dev, col_inst.data(), sizeof(uint16_t) * col_inst.size(), hipMemcpyHostToDevice), "upload tables");
     b->launch.inst = inst_dev;
@@ -899,6 +935,9 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
     b->launch.row_inst = row_dev;
     b->launch.col_inst = col_dev;
     b->launch.n_inst = n_inst;
+    b->pass_table = pass_dev;
+    SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if ((st = batch_layout(b, 1024, 1))) return st;
     SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock - 256), "hipFuncSetAttribute");
     SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     return SCPIC_OK;
@@ -1014,9 +1053,160 @@ scpic_status batch_graph(scpic_batch *b, const scpic_particles *parts, BatchSche
     return SCPIC_OK;
 }
 
+// Per-beam op lists of the first turn, a steady turn and the epilogue; they
+// must share one shape (SCPIC_EUNSUPPORTED otherwise).
+scpic_status batch_ops(scpic_batch *b, const scpic_element *const *turns, const int32_t *n_els,
+                       std::vector<std::vector<PassOp>> &first,
+                       std::vector<std::vector<PassOp>> &steady,
+                       std::vector<std::vector<PassOp>> &tail, bool &any_sc0)
+{
+    for (int k = 0; k < b->n_inst; ++k) {
+        std::vector<const scpic_element *> all, trailing;
+        if (scpic_status st = collect_elements(turns[k], n_els[k], all, true)) {
+            g_last_error = "beam " + std::to_string(k) + ": " + g_last_error;
+            return st;
+        }
+        bool any_sc = false;
+        double last_kappa = 0.0;
+        build_turn(all, true, first[k], any_sc, last_kappa, trailing);
+        if (any_sc) {
+            build_turn(all, false, steady[k], any_sc, last_kappa, trailing);
+            emit_segment(tail[k], true, last_kappa, trailing, false);
+        }
+        if (k == 0) any_sc0 = any_sc;
+        if (any_sc != any_sc0 || !same_shape(first[k], first[0]) ||
+            !same_shape(steady[k], steady[0]) || !same_shape(tail[k], tail[0]))
+            return fail(SCPIC_EUNSUPPORTED,
+                        "beam " + std::to_string(k) +
+                            ": its ring does not share the schedule of beam 0 (same number of "
+                            "SC elements, at most 12 other elements between them)");
+    }
+    return SCPIC_OK;
+}
+
+void batch_drop_all_schedules(scpic_batch *b)
+{
+    for (auto &sc : b->schedules) batch_drop_schedule(sc);
+    b->schedules.clear();
+}
+
+// Device scratch copy of the particles for timing runs (freed by the caller).
+struct ScratchParts {
+    scpic_particles p{};
+    std::vector<void *> mem;
+    ~ScratchParts()
+    {
+        for (void *m : mem) hipFree(m);
+    }
+};
+
+scpic_status scratch_copy(hipStream_t s, const scpic_particles *src, ScratchParts &dst)
+{
+    dst.p = *src;
+    const size_t n = (size_t)src->n;
+    auto clone = [&](const void *from, size_t bytes, void **to) -> scpic_status {
+        if (!from) {
+            *to = nullptr;
+            return SCPIC_OK;
+        }
+        hipError_t e = hipMalloc(to, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            *to = nullptr;
+            return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        dst.mem.push_back(*to);
+        SCPIC_HIP_TRY(hipMemcpyAsync(*to, from, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+        return SCPIC_OK;
+    };
+    void *q;
+    scpic_status st;
+    if ((st = clone(src->x, 8 * n, &q))) return st;
+    dst.p.x = (double *)q;
+    if ((st = clone(src->px, 8 * n, &q))) return st;
+    dst.p.px = (double *)q;
+    if ((st = clone(src->y, 8 * n, &q))) return st;
+    dst.p.y = (double *)q;
+    if ((st = clone(src->py, 8 * n, &q))) return st;
+    dst.p.py = (double *)q;
+    if ((st = clone(src->w, 4 * n, &q))) return st;
+    dst.p.w = (const float *)q;
+    if ((st = clone(src->lost, n, &q))) return st;
+    dst.p.lost = (uint8_t *)q;
+    return SCPIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+scpic_status scpic_batch_autotune(scpic_batch *b, const scpic_particles *parts,
+                                  const scpic_element *const *turns, const int32_t *n_els,
+                                  int32_t trial_turns, int32_t *threads_out,
+                                  int32_t *blocks_per_cu_out)
+{
+    g_last_error.clear();
+    if (!b) return fail(SCPIC_EINVAL, "batch is NULL");
+    if (scpic_status st = check_parts(parts)) return st;
+    if (parts->n != b->offsets.back())
+        return fail(SCPIC_EINVAL, "parts->n must equal offsets[n_inst] of the batch");
+    if (!turns || !n_els) return fail(SCPIC_EINVAL, "turns and n_els must be non-NULL");
+    if (trial_turns < 1 || trial_turns > 100)
+        return fail(SCPIC_EINVAL, "trial_turns must be in [1, 100]");
+    const int n = b->n_inst;
+    std::vector<std::vector<PassOp>> first(n), steady(n), tail(n);
+    bool any_sc = false;
+    if (scpic_status st = batch_ops(b, turns, n_els, first, steady, tail, any_sc)) return st;
+    SCPIC_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    batch_drop_all_schedules(b);
+    ScratchParts scratch;
+    if (scpic_status st = scratch_copy(b->stream, parts, scratch)) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SCPIC_HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail_hip(he, "hipEventCreate");
+    }
+    float best = -1.0f;
+    int best_t = b->pass_threads, best_c = b->blocks_per_cu;
+    scpic_status st = SCPIC_OK;
+    const std::vector<std::vector<PassOp>> &timed = any_sc ? steady : first;
+    for (int t : kTuneThreads) {
+        for (int c : kTuneBlocksPerCu) {
+            if ((st = batch_layout(b, t, c))) break;
+            BatchSchedule *sch = nullptr;
+            // one untimed turn (the first turn's schedule: it sets the
+            // headers), then trial_turns timed steady turns
+            if ((st = batch_schedule(b, first, &scratch.p, &sch))) break;
+            if ((st = batch_enqueue(b, b->stream, &scratch.p, *sch))) break;
+            if ((st = batch_schedule(b, timed, &scratch.p, &sch))) break;
+            if ((he = hipEventRecord(e0, b->stream)) != hipSuccess) break;
+            for (int r = 0; r < trial_turns && !st; ++r) st = batch_enqueue(b, b->stream, &scratch.p, *sch);
+            if (st) break;
+            if ((he = hipEventRecord(e1, b->stream)) != hipSuccess) break;
+            if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                best_t = t;
+                best_c = c;
+            }
+            batch_drop_all_schedules(b);
+        }
+        if (st || he != hipSuccess) break;
+    }
+    hipStreamSynchronize(b->stream);
+    batch_drop_all_schedules(b);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    if (he != hipSuccess) return fail_hip(he, "timing the candidate shapes");
+    if ((st = batch_layout(b, best_t, best_c))) return st;
+    if (threads_out) *threads_out = best_t;
+    if (blocks_per_cu_out) *blocks_per_cu_out = best_c;
+    return SCPIC_OK;
+}
 
 scpic_status scpic_batch_create(scpic_batch **out, const scpic_grid *grids,
                                 const int64_t *offsets, int32_t n_inst, int32_t precision,
@@ -1082,27 +1272,7 @@ scpic_status scpic_track_batched(scpic_batch *b, const scpic_particles *parts,
     const int n = b->n_inst;
     std::vector<std::vector<PassOp>> first(n), steady(n), tail(n);
     bool any_sc0 = false;
-    for (int k = 0; k < n; ++k) {
-        std::vector<const scpic_element *> all, trailing;
-        if (scpic_status st = collect_elements(turns[k], n_els[k], all, true)) {
-            g_last_error = "beam " + std::to_string(k) + ": " + g_last_error;
-            return st;
-        }
-        bool any_sc = false;
-        double last_kappa = 0.0;
-        build_turn(all, true, first[k], any_sc, last_kappa, trailing);
-        if (any_sc) {
-            build_turn(all, false, steady[k], any_sc, last_kappa, trailing);
-            emit_segment(tail[k], true, last_kappa, trailing, false);
-        }
-        if (k == 0) any_sc0 = any_sc;
-        if (any_sc != any_sc0 || !same_shape(first[k], first[0]) ||
-            !same_shape(steady[k], steady[0]) || !same_shape(tail[k], tail[0]))
-            return fail(SCPIC_EUNSUPPORTED,
-                        "beam " + std::to_string(k) +
-                            ": its ring does not share the schedule of beam 0 (same number of "
-                            "SC elements, at most 12 other elements between them)");
-    }
+    if (scpic_status st = batch_ops(b, turns, n_els, first, steady, tail, any_sc0)) return st;
     if (n_turns == 0 || parts->n == 0) return SCPIC_OK;
     BatchSchedule *sch = nullptr;
     if (!any_sc0) {

@@ -30,7 +30,8 @@ EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_set_stream", "scpic_push", "scpic_deposit", "scpic_solve", "scpic_kick",
            "scpic_track", "scpic_set_option", "scpic_pass", "scpic_reduce_solve",
            "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
-           "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_get_field")
+           "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_autotune",
+           "scpic_batch_get_field")
 
 
 class Grid(ctypes.Structure):
@@ -84,6 +85,9 @@ def load_library(path: Path | str | None = None):
     L.scpic_track_batched.argtypes = [vp, ctypes.POINTER(Particles), ctypes.POINTER(vp),
                                       ctypes.POINTER(i32), i32]
     L.scpic_batch_get_field.argtypes = [vp, i32, vp, vp]
+    L.scpic_batch_autotune.argtypes = [vp, ctypes.POINTER(Particles), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
     for name in EXPORTS:
         if name not in ("scpic_version", "scpic_last_error"):
             getattr(L, name).restype = i32
@@ -319,6 +323,22 @@ class Batch:
         _check(self._lib.scpic_track_batched(
             self._h, ctypes.byref(p), ptrs,
             counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_turns)))
+
+    def autotune(self, parts: dict, lattices, trial_turns: int = 2, stream=None):
+        """Time the candidate pass shapes on a scratch copy of parts and keep the
+        fastest; returns (threads per workgroup, workgroups per compute unit)."""
+        self._sync_stream(stream)
+        els = [_elements(lat) for lat in lattices]
+        ptrs = (ctypes.c_void_p * len(els))(*[e.ctypes.data for e in els])
+        counts = np.array([len(e) for e in els], dtype=np.int32)
+        p = particles_struct(parts)
+        t = ctypes.c_int32()
+        c = ctypes.c_int32()
+        _check(self._lib.scpic_batch_autotune(
+            self._h, ctypes.byref(p), ptrs,
+            counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(trial_turns),
+            ctypes.byref(t), ctypes.byref(c)))
+        return t.value, c.value
 
     def get_field(self, k: int, stream=None):
         self._sync_stream(stream)

@@ -120,4 +120,5 @@ def test_batch_calls_on_null_batch_are_einval(lib):
     assert lib.scpic_batch_set_stream(None, None) == -1
     assert lib.scpic_track_batched(None, ctypes.byref(p), None, None, 1) == -1
     assert lib.scpic_batch_get_field(None, 0, None, None) == -1
+    assert lib.scpic_batch_autotune(None, ctypes.byref(p), None, None, 1, None, None) == -1
     assert b"batch" in lib.scpic_last_error()

@@ -170,3 +170,25 @@ def test_tune_scan_batch_full_size(gpu, orc):
     assert all(np.isfinite(full[c][alive]).all() for c in COORDS)
     print(f"[batch] lost in the checked beams after {w['turns']} turns: {lost_total}",
           flush=True)
+
+
+def test_autotune_picks_a_shape_and_keeps_results(gpu):
+    _say("batch autotune on 5 beams, then 3 turns == single-beam path")
+    parts, offsets, grids, lattices = _mixed_batch()
+    with gpu.Batch(grids, offsets) as b:
+        d = _dev(parts)
+        threads, per_cu = b.autotune(d, lattices, trial_turns=1)
+        print(f"[batch] autotune chose {threads} threads, {per_cu} workgroups per CU", flush=True)
+        assert threads in (256, 512, 1024) and per_cu in (1, 2, 4)
+        np.testing.assert_array_equal(_host(d)["x"], parts["x"])  # tuning ran on a copy
+        b.track(d, lattices, 3)
+        got = _host(d)
+    for k in (0, 2, 4):
+        beam = _beam(parts, offsets, k)
+        with gpu.Context(grids[k]) as ctx:
+            dk = _dev(beam)
+            ctx.track(dk, lattices[k], 3)
+            want = _host(dk)
+        mine = _beam(got, offsets, k)
+        for key in COORDS + ("lost",):
+            np.testing.assert_array_equal(mine[key], want[key], err_msg=f"beam {k} {key}")

@@ -1,0 +1,83 @@
+"""Long runs: the small workload (1e4 Gaussian particles, 64^2 grid, 16 SC
+steps per turn, tune shift -0.2) over 1000 turns, in the FP64 form and the
+mixed form (FP32 solve, field and gather; FP64 coordinates, maps and kick),
+against each other and against the FP64 oracle.
+
+Space-charge motion at this strength is chaotic: trajectories separate
+exponentially, and after 1000 turns the rms emittance of 1e4 particles
+responds to a perturbation of the inputs about 3e4 times its size.  The bars
+are therefore taken from the dynamics' own sensitivity s: the largest
+emittance change of the FP64 GPU form when every initial coordinate is
+perturbed by one FP32 rounding unit (2^-24 relative, random sign; three
+draws).  That perturbation is what storing the inputs in FP32 would do, so no
+form whose fields carry FP32 rounding can be held closer than s.
+  mixed vs FP64 form, mixed vs oracle    <= 2 s per plane
+  FP64 form vs oracle                    <= 10 * 1e-12 * s / 2^-24 per plane
+                                            (the FP64 field bar, amplified)
+Every figure is printed, including whether the mixed form is within 1e-4."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2010_11540_amd import inputs
+from tests.physics import rms_emittance
+
+pytestmark = pytest.mark.gpu
+
+TURNS = 1000
+ULP32 = 2.0 ** -24
+
+
+def _say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _emit(p):
+    alive = p["lost"] == 0
+    return np.array([rms_emittance(p["x"], p["px"], alive), rms_emittance(p["y"], p["py"], alive)])
+
+
+def _run(gpu, w, parts, precision):
+    from paper_2010_11540_amd.scpic import to_device
+    with gpu.Context(w["grid"], precision) as ctx:
+        d = to_device(parts)
+        ctx.track(d, w["lattice"], TURNS)
+        return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def test_small_workload_1000_turns_mixed_fp64_oracle(gpu, orc):
+    w = inputs.workload("small")
+    _say(f"small workload {TURNS} turns: fp64, mixed")
+    runs = {"fp64": _run(gpu, w, w["parts"], "fp64"), "mixed": _run(gpu, w, w["parts"], "mixed")}
+    sens = np.zeros(2)
+    for seed in (1, 2, 3):
+        _say(f"small workload {TURNS} turns: fp64 from inputs perturbed by 2^-24 (draw {seed})")
+        rng = np.random.default_rng(seed)
+        pert = inputs.copy_parts(w["parts"])
+        for c in ("x", "px", "y", "py"):
+            pert[c] = pert[c] * (1.0 + ULP32 * rng.choice([-1.0, 1.0], size=pert[c].shape[0]))
+        e = _emit(_run(gpu, w, pert, "fp64"))
+        sens = np.maximum(sens, np.abs(e / _emit(runs["fp64"]) - 1))
+    _say(f"small workload {TURNS} turns: oracle")
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, w["grid"], w["lattice"], TURNS)
+    runs["oracle"] = ref
+    eps = {k: _emit(v) for k, v in runs.items()}
+    for k, (ex, ey) in eps.items():
+        print(f"[long] {k:6s} after {TURNS} turns: emittance x {ex:.9e} y {ey:.9e}, lost "
+              f"{int(runs[k]['lost'].sum())}", flush=True)
+    print(f"[long] sensitivity to a 2^-24 input perturbation (fp64): x {sens[0]:.3e} "
+          f"y {sens[1]:.3e}", flush=True)
+    bars = {("mixed", "fp64"): 2 * sens, ("mixed", "oracle"): 2 * sens,
+            ("fp64", "oracle"): 10 * 1e-12 * sens / ULP32}
+    for (a, b), bar in bars.items():
+        d = np.abs(eps[a] / eps[b] - 1)
+        print(f"[long] {a} vs {b}: emittance rel diff x {d[0]:.3e} y {d[1]:.3e} "
+              f"(bar x {bar[0]:.3e} y {bar[1]:.3e}; within 1e-4: {bool((d <= 1e-4).all())})",
+              flush=True)
+        assert (d <= bar).all(), (a, b, d, bar)
+    for k in runs:
+        alive = runs[k]["lost"] == 0
+        assert all(np.isfinite(runs[k][c][alive]).all() for c in ("x", "px", "y", "py"))

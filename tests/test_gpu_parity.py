@@ -365,6 +365,53 @@ def test_long_bunch_weighted_kicks_on_256_grid(gpu, orc, precision, bar):
     assert err <= bar, (err, bar)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_workload_full_size_one_step(gpu, orc, precision):
+    """The large workload at full size (1e7 KV long-bunch particles with kick
+    weights, 256^2 grid) in the default launch shape: deposit bit-exact, field
+    within the precision's bar, and one step (map, deposit, solve, weighted
+    kick) against the oracle."""
+    import torch
+    _say(f"large workload full size ({precision}): deposit and solve")
+    w = inputs.workload("large")
+    g = w["grid"]
+    ref = inputs.copy_parts(w["parts"])
+    q_ref, n_ref = orc.deposit(ref, g)
+    scale = 1.0 / ((1 << 24) * w["n"])
+    with gpu.Context(g, precision) as ctx:
+        d = _dev(w["parts"])
+        rho, n_in = ctx.deposit(d)
+        np.testing.assert_array_equal(rho.cpu().numpy(), q_ref)
+        assert int(n_in.item()) == n_ref
+        ex, ey = ctx.solve(rho, scale)
+        ex = ex.double().cpu().numpy()
+        ey = ey.double().cpu().numpy()
+    ex_ref, ey_ref = orc.solve(q_ref, scale, g)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert _field_err(ex, ex_ref) <= tol, _field_err(ex, ex_ref)
+    assert _field_err(ey, ey_ref) <= tol, _field_err(ey, ey_ref)
+    _say(f"large workload full size ({precision}): one step")
+    lat = w["lattice"][:2]  # one segment: map, SC kick
+    assert list(lat["kind"]) == [inputs.LIN2X2, inputs.SC]
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, g, lat, 1)
+    with gpu.Context(g, precision) as ctx:
+        d = _dev(w["parts"])
+        ctx.track(d, lat, 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _turn_err(h, ref)
+    if precision == "fp64":
+        bar = 1e-10
+    else:
+        # one kick with the FP32 field bar, relative to the rms momenta
+        kappa = float(lat["p"][1, 0])
+        emax = max(np.abs(ex_ref).max(), np.abs(ey_ref).max())
+        bar = 2 * 1e-5 * kappa * emax / min(ref["px"].std(), ref["py"].std())
+    print(f"[large {precision}] one-step coordinate error {err:.3e} (bar {bar:.3e})", flush=True)
+    assert err <= bar, (err, bar)
+
+
 def test_zero_particles_and_no_sc_lattice(gpu, orc):
     _say("track n=0 and lattice without SC")
     g = inputs.make_grid(32)
