@@ -22,6 +22,8 @@
 // the potential out of the field's rounding, which matters for the FP32 form.
 // Every kernel issues all of its global loads into registers before the
 // first LDS write, so each kernel waits for one round of memory latency.
+#include <algorithm>
+
 #include "scpic_internal.h"
 
 namespace scpic {
@@ -115,51 +117,89 @@ constexpr int kMaxPerThread = kMaxFft / 64;
 
 // Exact sum of grid row i over the partials of nblocks workgroups plus the
 // carry grid (which is cleared), for the ny cells of the row.  Called by all
-// kRowThreads threads.  Thread t reads 16-byte chunks (4 cells) of the row:
+// NT threads of the workgroup (NT >= ny).  Thread t reads 16-byte chunks (4 cells) of the row:
 // ny/4 lanes cover one workgroup's row segment and the kRowThreads/(ny/4)
 // groups of lanes split the workgroups, each issuing all of its loads before
 // adding any (one round of memory latency for <= kReduceChunk workgroups per
 // lane).  Chunks outside a workgroup's bounding box are not read; cells of a
 // chunk outside it are masked.  hdr: the headers staged in LDS; red: LDS
-// scratch of kRowThreads * 4 uint64; carry_v: this cell's carry, loaded by
+// scratch of NT * 4 uint64; carry_v: this cell's carry, loaded by
 // the caller with its first round of loads (cleared here when nonzero).
 // Returns the total of cell tid (tid < ny).
 constexpr int kReduceChunk = 8;
 
-__device__ unsigned long long reduce_row(const DepositTarget &dep, const BlockHeader *hdr,
-                                         unsigned long long *red, int nblocks, int i, int ny,
-                                         int tid, unsigned long long carry_v)
+// Lane layout of a row reduction by NT threads: lanes = ny/4 16-byte chunks
+// cover one workgroup's row segment, and groups = NT/lanes groups of lanes
+// split the workgroups.
+struct RowLanes {
+    int lanes, groups, grp, j0c;
+};
+template <int NT>
+__device__ __forceinline__ RowLanes row_lanes(int ny, int tid)
 {
-    const int lanes = ny >> 2;              // 16-byte chunks per row segment
-    const int groups = kRowThreads / lanes;  // ny <= 256 -> at least 16
-    const int grp = tid / lanes, c4 = tid - grp * lanes;
-    const int j0c = c4 * 4;
+    RowLanes r;
+    r.lanes = ny >> 2;
+    r.groups = NT / r.lanes;  // ny <= 256 -> at least NT / 64
+    r.grp = tid / r.lanes;
+    r.j0c = (tid - r.grp * r.lanes) * 4;
+    return r;
+}
+
+// The lane's first round of partial loads (workgroups grp + u * groups,
+// u < kReduceChunk).  Every slice address is valid whatever the headers say
+// (workgroups past nblocks read slice 0), so these loads can go out with the
+// headers' loads, before the headers are known; chunks outside a workgroup's
+// box are masked afterwards.
+template <int NT>
+__device__ __forceinline__ void prefetch_row(const DepositTarget &dep, int nblocks, int i, int ny,
+                                             int tid, uint4 (&v)[kReduceChunk])
+{
+    const RowLanes L = row_lanes<NT>(ny, tid);
+    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + L.j0c;
+#pragma unroll
+    for (int u = 0; u < kReduceChunk; ++u) {
+        const int b = L.grp + u * L.groups;
+        v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(b < nblocks ? b : 0) * ny);
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ unsigned long long reduce_row(const DepositTarget &dep,
+                                                         const BlockHeader *hdr,
+                                                         unsigned long long *red, int nblocks,
+                                                         int i, int ny, int tid,
+                                                         unsigned long long carry_v,
+                                                         const uint4 (&first)[kReduceChunk])
+{
+    const RowLanes L = row_lanes<NT>(ny, tid);
+    const int groups = L.groups, grp = L.grp, j0c = L.j0c;
     unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
-    for (int b0 = grp; b0 < nblocks; b0 += groups * kReduceChunk) {
-        uint4 v[kReduceChunk];
-        int lo[kReduceChunk], hi[kReduceChunk];
-        // Branch-free: every lane issues its loads back to back (a chunk
-        // outside a box is read from workgroup 0's slice, always valid, and
-        // masked), so the compiler does not wait between them.
+    // add the chunks of workgroups b0 + u * groups that fall inside their box
+    auto add = [&](const uint4 (&v)[kReduceChunk], int b0) {
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
             const int b = b0 + u * groups;
-            const int bc = b < nblocks ? b : 0;
-            const BlockHeader h = hdr[bc];
+            const BlockHeader h = hdr[b < nblocks ? b : 0];
             const bool take = b < nblocks && i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 &&
                               j0c <= h.j1;
-            lo[u] = take ? h.j0 : 0;
-            hi[u] = take ? h.j1 : -1;
-            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(take ? bc : 0) * ny);
+            const int lo = take ? h.j0 : 0, hi = take ? h.j1 : -1;
+            s0 += (j0c + 0 >= lo && j0c + 0 <= hi) ? v[u].x : 0u;
+            s1 += (j0c + 1 >= lo && j0c + 1 <= hi) ? v[u].y : 0u;
+            s2 += (j0c + 2 >= lo && j0c + 2 <= hi) ? v[u].z : 0u;
+            s3 += (j0c + 3 >= lo && j0c + 3 <= hi) ? v[u].w : 0u;
         }
+    };
+    add(first, grp);
+    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
+    for (int b0 = grp + groups * kReduceChunk; b0 < nblocks; b0 += groups * kReduceChunk) {
+        // branch-free: workgroups past nblocks read slice 0 (valid, masked)
+        uint4 v[kReduceChunk];
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
-            s0 += (j0c + 0 >= lo[u] && j0c + 0 <= hi[u]) ? v[u].x : 0u;
-            s1 += (j0c + 1 >= lo[u] && j0c + 1 <= hi[u]) ? v[u].y : 0u;
-            s2 += (j0c + 2 >= lo[u] && j0c + 2 <= hi[u]) ? v[u].z : 0u;
-            s3 += (j0c + 3 >= lo[u] && j0c + 3 <= hi[u]) ? v[u].w : 0u;
+            const int b = b0 + u * groups;
+            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(b < nblocks ? b : 0) * ny);
         }
+        add(v, b0);
     }
     unsigned long long *mine = red + (size_t)grp * ny + j0c;
     mine[0] = s0;
@@ -185,9 +225,12 @@ __global__ void __launch_bounds__(kRowThreads)
     __shared__ unsigned long long red[kRowThreads * 4];
     const int tid = threadIdx.x, i = blockIdx.x;
     const unsigned long long cv = tid < ny ? dep.carry[(size_t)i * ny + tid] : 0ull;
+    uint4 first[kReduceChunk];
+    prefetch_row<kRowThreads>(dep, nblocks, i, ny, tid, first);
     for (int b = tid; b < nblocks; b += kRowThreads) hdr[b] = dep.header[b];
     __syncthreads();
-    const unsigned long long t = reduce_row(dep, hdr, red, nblocks, i, ny, tid, cv);
+    const unsigned long long t =
+        reduce_row<kRowThreads>(dep, hdr, red, nblocks, i, ny, tid, cv, first);
     if (tid < ny) q[(size_t)i * ny + tid] = (int64_t)t;
     if (n_in != nullptr && i == 0 && tid < 64) {
         long long cnt = 0;
@@ -203,7 +246,15 @@ __global__ void __launch_bounds__(kRowThreads)
 // (m < ny/2; zero up to ny), Z = FFT_ny(z), then
 //   X[l] = (Z[l] + conj Z[ny-l]) / 2 - i W^l (Z[l] - conj Z[ny-l]) / 2,
 // W = exp(-2 pi i / my), for l = 0..ny.
-template <typename T, bool FROM_PARTIALS>
+// LDS of the row-forward workgroup: twiddles [my], two FFT buffers [ny],
+// rho [ny], then (16-byte aligned) the staged headers.
+template <typename T>
+__host__ __device__ constexpr size_t rows_fwd_hdr_offset(int ny, int my)
+{
+    return (sizeof(cx<T>) * (size_t)(my + 2 * ny) + sizeof(T) * (size_t)ny + 15) & ~(size_t)15;
+}
+
+template <typename T, bool FROM_PARTIALS, int NT>
 __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblocks,
                                               const int64_t *__restrict__ q, double scale, int nx,
                                               int ny, int my, int log2my,
@@ -215,22 +266,22 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
     cx<T> *a = twl + my;                                // ny
     cx<T> *b = a + ny;                                  // ny
     T *rho = reinterpret_cast<T *>(b + ny);             // ny
-    __shared__ BlockHeader hdr[FROM_PARTIALS ? kMaxPassBlocks : 1];
-    __shared__ unsigned long long red[FROM_PARTIALS ? kRowThreads * 4 : 1];
+    BlockHeader *hdr = reinterpret_cast<BlockHeader *>(smem_raw + rows_fwd_hdr_offset<T>(ny, my));
+    __shared__ unsigned long long red[FROM_PARTIALS ? NT * 4 : 1];
     const int tid = threadIdx.x;
-    // one round of loads: twiddles, and the headers or the dense row
-    // (my <= 512 and nblocks <= 512 are below kRowThreads)
-    const cx<T> tv = tid < my ? tw[tid] : cx<T>{T(0), T(0)};
+    // one round of loads: twiddles, and the headers or the dense row (ny <= NT)
     const int64_t qv = (!FROM_PARTIALS && tid < ny) ? q[(size_t)i * ny + tid] : 0;
     const unsigned long long cv =
         (FROM_PARTIALS && tid < ny) ? dep.carry[(size_t)i * ny + tid] : 0ull;
-    BlockHeader hv{};
-    if (FROM_PARTIALS && tid < nblocks) hv = dep.header[tid];
-    if (FROM_PARTIALS && tid < nblocks) hdr[tid] = hv;
-    if (tid < my) twl[tid] = tv;
+    uint4 first[kReduceChunk];
+    if (FROM_PARTIALS) prefetch_row<NT>(dep, nblocks, i, ny, tid, first);
+    for (int t = tid; t < my; t += NT) twl[t] = tw[t];
+    if (FROM_PARTIALS)
+        for (int t = tid; t < nblocks; t += NT) hdr[t] = dep.header[t];
     if (FROM_PARTIALS) {
         __syncthreads();
-        const unsigned long long t = reduce_row(dep, hdr, red, nblocks, i, ny, tid, cv);
+        const unsigned long long t =
+            reduce_row<NT>(dep, hdr, red, nblocks, i, ny, tid, cv, first);
         if (tid < ny) rho[tid] = (T)((double)t * scale);
     } else {
         if (tid < ny) rho[tid] = (T)((double)qv * scale);
@@ -239,9 +290,8 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
     const int half = ny;  // complex length: my / 2
     if (tid < half)
         a[tid] = (2 * tid + 1 < ny) ? cx<T>{rho[2 * tid], rho[2 * tid + 1]} : cx<T>{T(0), T(0)};
-    const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, kRowThreads);
-    if (tid <= ny) {
-        const int l = tid;
+    const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, NT);
+    for (int l = tid; l <= ny; l += NT) {
         const cx<T> zl = Z[l & (half - 1)];
         const cx<T> zm = conj(Z[(half - l) & (half - 1)]);
         const cx<T> s = zl + zm, d = zl - zm;
@@ -256,19 +306,23 @@ __global__ void __launch_bounds__(kRowThreads)
                int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
                cx<T> *__restrict__ at)
 {
-    rows_fwd_body<T, FROM_PARTIALS>(dep, nblocks, q, scale, nx, ny, my, log2my, tw, at,
-                                    (int)blockIdx.x);
+    rows_fwd_body<T, FROM_PARTIALS, kRowThreads>(dep, nblocks, q, scale, nx, ny, my, log2my, tw,
+                                                 at, (int)blockIdx.x);
 }
 
 // Every beam of a batch: workgroup -> (beam, row) from the batch's row table;
-// the rows come from the partials of the beam's last batched pass.
+// the rows come from the partials of the beam's last batched pass.  A beam's
+// row has few partial slices, so a smaller workgroup does it and more of them
+// fit on a compute unit at once.
+constexpr int kBatchRowThreads = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(kRowThreads) k_rows_fwd_batched(BatchLaunch b)
+__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b)
 {
     const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
-    rows_fwd_body<T, true>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny, I.my, I.log2_my,
-                           (const cx<T> *)I.tw_y, (cx<T> *)I.spec_a,
-                           (int)blockIdx.x - I.row_block0);
+    rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
+                                             I.my, I.log2_my, (const cx<T> *)I.tw_y,
+                                             (cx<T> *)I.spec_a, (int)blockIdx.x - I.row_block0);
 }
 
 // Column l of the row spectra: forward FFT along x, times the Green's
@@ -450,7 +504,8 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
                           int nblocks, const int64_t *q, double scale, void *ex, void *ey,
                           void *ef)
 {
-    const size_t row_lds = sizeof(cx<T>) * (size_t)(w.my + 2 * w.ny) + sizeof(T) * (size_t)w.ny;
+    const size_t row_lds = rows_fwd_hdr_offset<T>(w.ny, w.my) +
+                           (FROM_PARTIALS ? sizeof(BlockHeader) * (size_t)std::max(nblocks, 1) : 0);
     hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx), dim3(kRowThreads), row_lds, s,
                        dep, nblocks, q, scale, w.nx, w.ny, w.my, w.log2_my,
                        (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a);
@@ -461,13 +516,14 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
 
 template <typename T>
 hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows, int cols,
-                                  int max_nx, int max_ny)
+                                  int max_nx, int max_ny, int max_pass_blocks)
 {
     const int mmx = 2 * max_nx, mmy = 2 * max_ny;
-    const size_t row_lds = sizeof(cx<T>) * (size_t)(mmy + 2 * max_ny) + sizeof(T) * (size_t)max_ny;
+    const size_t row_lds = rows_fwd_hdr_offset<T>(max_ny, mmy) +
+                           sizeof(BlockHeader) * (size_t)std::max(max_pass_blocks, 1);
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
     const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)mmy;
-    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kRowThreads), row_lds, s, b);
+    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kBatchRowThreads), row_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cols_batched<T>, dim3(cols), dim3(kColThreads), col_lds, s, b);
@@ -480,10 +536,10 @@ hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows,
 }  // namespace
 
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny)
+                                int cols, int max_nx, int max_ny, int max_pass_blocks)
 {
-    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny)
-                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny);
+    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks)
+                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks);
 }
 
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,

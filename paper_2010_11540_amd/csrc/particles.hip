@@ -95,23 +95,45 @@ __device__ __forceinline__ void apply_element(int kind, const double *__restrict
     }
 }
 
+// Reductions over the 64 lanes of a wave with DPP row operations (no LDS
+// traffic): the two quad permutations and the half-row and row mirrors leave
+// every lane of a row of 16 holding its row's result; row broadcast 15 folds
+// row 0 into row 1 and row 2 into row 3, row broadcast 31 folds row 1 into
+// rows 2 and 3, so lane 63 holds the wave's result.  Rows a step does not
+// write keep their value (the identity of the step's operation).
+template <typename Op>
+__device__ __forceinline__ int wave_reduce(int v, int identity, Op op)
+{
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, kWave - 1);
+}
 __device__ __forceinline__ int wave_min(int v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
+    return wave_reduce(v, INT_MAX, [](int a, int b) { return min(a, b); });
 }
 __device__ __forceinline__ int wave_max(int v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
+    return wave_reduce(v, INT_MIN, [](int a, int b) { return max(a, b); });
 }
 __device__ __forceinline__ int wave_sum(int v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    return wave_reduce(v, 0, [](int a, int b) { return a + b; });
+}
+
+// t / w for 0 <= t < 2^16 and 1 <= w <= 2^16: the float product with the
+// rounded reciprocal is within 0.01 of the quotient, so one integer step
+// either way makes it exact.
+__device__ __forceinline__ int div_small(int t, int w, float inv_w)
+{
+    int r = (int)((float)t * inv_w);
+    r -= (r * w > t) ? 1 : 0;
+    r += ((r + 1) * w <= t) ? 1 : 0;
+    return r;
 }
 
 // A rectangle of grid nodes held in LDS: rows i0..i0+h-1, columns
@@ -249,21 +271,25 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         staged = known &&
                  ((size_t)ebox.h * ebox.w + 2) * sizeof(V) + tile_bytes <= (size_t)lds_bytes;
         if (staged) {
-            // four nodes per thread per round, all loads before the stores
+            // four nodes per thread per round; indices past the box repeat
+            // its last node, so every load and store is unconditional and
+            // the four loads are in flight before the first store
             const V *ev = reinterpret_cast<const V *>(ef);
             const int nodes = ebox.h * ebox.w;
             const int nt = (int)blockDim.x;
+            const float inv_w = 1.0f / (float)ebox.w;
+            auto node = [&](int t) {
+                const int r = div_small(t, ebox.w, inv_w);
+                return (ebox.i0 + r) * g.ny + ebox.j0 + (t - r * ebox.w);
+            };
             for (int t0 = threadIdx.x; t0 < nodes; t0 += 4 * nt) {
-                V v[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int t = min(t0 + k * nt, nodes - 1);
-                    const int r = t / ebox.w;
-                    v[k] = ev[(ebox.i0 + r) * g.ny + ebox.j0 + (t - r * ebox.w)];
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (t0 + k * nt < nodes) le[t0 + k * nt] = v[k];
+                const int ta = t0, tb = min(t0 + nt, nodes - 1), tc = min(t0 + 2 * nt, nodes - 1),
+                          td = min(t0 + 3 * nt, nodes - 1);
+                const V va = ev[node(ta)], vb = ev[node(tb)], vc = ev[node(tc)], vd = ev[node(td)];
+                le[ta] = va;
+                le[tb] = vb;
+                le[tc] = vc;
+                le[td] = vd;
             }
         }
     }
@@ -385,8 +411,9 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         if (i0 <= i1) {
             const int c0 = j0 >> 2, nch = (j1 >> 2) - c0 + 1;
             const int total = (i1 - i0 + 1) * nch;
+            const float inv_nch = 1.0f / (float)nch;
             for (int t = threadIdx.x; t < total; t += blockDim.x) {
-                const int r = t / nch;
+                const int r = div_small(t, nch, inv_nch);
                 const int i = i0 + r, cc = c0 + (t - r * nch);
                 const uint4 v = *reinterpret_cast<const uint4 *>(lq + tile.at(i, 4 * cc));
                 reinterpret_cast<uint4 *>(dep.partial +

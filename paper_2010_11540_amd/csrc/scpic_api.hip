@@ -740,6 +740,7 @@ struct scpic_batch {
     std::vector<BatchInstance> inst;  // host copy of the device table
     BatchLaunch launch{};
     int total_pass_blocks = 0, total_rows = 0, total_cols = 0, max_nx = 0, max_ny = 0;
+    int max_beam_blocks = 0;  // most pass workgroups of one beam in the current layout
     std::vector<void *> allocations;
     std::vector<BatchSchedule> schedules;
     uint64_t use_counter = 0;
@@ -776,16 +777,50 @@ void batch_free_all(scpic_batch *b)
     b->capture_stream = nullptr;
 }
 
-// Workgroups of beam k in a batched pass: in proportion to its particles so
-// that the whole batch takes about `slots` workgroups (blocks_per_cu per
-// compute unit), at least one per non-empty beam, at most one per `threads`
-// particles.
+// Upper bound of beam k's workgroups in a batched pass of `slots`
+// workgroups: its proportional share rounded up, at most one per `threads`
+// particles, at least one for a non-empty beam (sizes the partial slices).
 int batch_pass_blocks(int64_t n_k, int64_t total, int64_t slots, int threads)
 {
     if (n_k <= 0) return 0;
     const int64_t share = (n_k * slots + total - 1) / total;
     const int64_t need = (n_k + threads - 1) / threads;
     return (int)std::max<int64_t>(1, std::min<int64_t>({share, need, (int64_t)kMaxPassBlocks}));
+}
+
+// Workgroups per beam for a batched pass of about `slots` workgroups in all:
+// one per non-empty beam, then each further workgroup to the beam with the
+// most particles per workgroup (which minimises the largest workgroup's
+// share, so the pass ends with one round of equal workgroups), within the
+// caps (one per `threads` particles, the allocated slices).
+std::vector<int> batch_assign_blocks(const std::vector<int64_t> &n, int64_t slots, int threads,
+                                     const std::vector<int> &cap)
+{
+    const size_t k_n = n.size();
+    std::vector<int> blocks(k_n, 0);
+    int64_t used = 0;
+    for (size_t k = 0; k < k_n; ++k)
+        if (n[k] > 0) {
+            blocks[k] = 1;
+            ++used;
+        }
+    while (used < slots) {
+        size_t best = k_n;
+        double best_load = 0.0;
+        for (size_t k = 0; k < k_n; ++k) {
+            if (blocks[k] == 0 || blocks[k] >= cap[k]) continue;
+            if ((int64_t)blocks[k] * threads >= n[k]) continue;
+            const double load = (double)n[k] / blocks[k];
+            if (load > best_load) {
+                best_load = load;
+                best = k;
+            }
+        }
+        if (best == k_n) break;
+        ++blocks[best];
+        ++used;
+    }
+    return blocks;
 }
 
 // Candidate launch shapes of the batched pass (threads per workgroup,
@@ -799,16 +834,19 @@ constexpr int kMinTuneThreads = 256, kMaxTuneBlocksPerCu = 4;
 // "unknown" (their boxes belonged to the previous assignment of particles).
 scpic_status batch_layout(scpic_batch *b, int threads, int blocks_per_cu)
 {
-    const int64_t total = b->offsets.back();
+    std::vector<int64_t> sizes(b->n_inst);
+    for (int k = 0; k < b->n_inst; ++k) sizes[k] = b->inst[k].n;
+    const std::vector<int> blocks =
+        batch_assign_blocks(sizes, (int64_t)b->n_cu * blocks_per_cu, threads, b->max_slices);
     std::vector<uint16_t> pass_inst;
     b->total_pass_blocks = 0;
+    b->max_beam_blocks = 0;
     for (int k = 0; k < b->n_inst; ++k) {
         BatchInstance &I = b->inst[k];
-        I.pass_blocks = std::min(
-            b->max_slices[k],
-            batch_pass_blocks(I.n, total, (int64_t)b->n_cu * blocks_per_cu, threads));
+        I.pass_blocks = blocks[k];
         I.pass_block0 = b->total_pass_blocks;
         b->total_pass_blocks += I.pass_blocks;
+        b->max_beam_blocks = std::max(b->max_beam_blocks, I.pass_blocks);
         for (int t = 0; t < I.pass_blocks; ++t) pass_inst.push_back((uint16_t)k);
         SCPIC_HIP_TRY(hipMemsetAsync(I.dep.header, 0xff, sizeof(BlockHeader) * I.dep.max_blocks, b->stream), "hipMemsetAsync");
     }
@@ -1022,7 +1060,7 @@ scpic_status batch_enqueue(scpic_batch *b, hipStream_t s, const scpic_particles 
         if (e != hipSuccess) return fail_hip(e, "batched pass launch");
         if (op.deposit) {
             e = launch_solve_batched(s, b->launch, b->mixed, b->total_rows, b->total_cols,
-                                     b->max_nx, b->max_ny);
+                                     b->max_nx, b->max_ny, b->max_beam_blocks);
             if (e != hipSuccess) return fail_hip(e, "batched solve launch");
         }
     }
