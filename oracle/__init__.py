@@ -16,7 +16,9 @@ What each function follows (arXiv:2010.11540):
               nodes of a cell, in 2^-24 fixed-point charge units.
   potential   open-boundary Poisson solve by convolution with the free-space
               Green's function -ln r (Hockney's method, cited in Sec. I), as a
-              direct sum over charged nodes.
+              direct sum over charged nodes; or the grounded rectangular pipe
+              of Sec. IV-B (5-point Laplacian, u = 0 on the walls), written out
+              as its discrete sine-eigenvector expansion.
   field       E = -grad(u) (Sec. IV-C), by centred differences on the nodes.
   kick        Sec. IV: transverse kick proportional to the field at the
               particle times the distance since the previous kick, and (2.5D
@@ -70,16 +72,18 @@ def lib():
         L.orc_green.restype = dbl
         L.orc_potential.argtypes = [vp, dbl, i32, i32, dbl, dbl, vp]
         L.orc_potential.restype = None
+        L.orc_potential_pipe.argtypes = [vp, dbl, i32, i32, dbl, dbl, vp]
+        L.orc_potential_pipe.restype = None
         L.orc_field.argtypes = [vp, i32, i32, dbl, dbl, vp, vp]
         L.orc_field.restype = None
         L.orc_kick.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp,
                                dbl]
         L.orc_kick.restype = None
         L.orc_space_charge.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
-                                       dbl, dbl, vp, vp]
+                                       dbl, dbl, vp, vp, i32]
         L.orc_space_charge.restype = i64
         L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, vp,
-                                vp, i32]
+                                vp, i32, i32]
         L.orc_track.restype = None
         _lib = L
     return _lib
@@ -134,13 +138,15 @@ def green(di: int, dj: int, dx: float, dy: float) -> float:
     return lib().orc_green(di, dj, dx, dy)
 
 
-def potential(q: np.ndarray, scale: float, grid) -> np.ndarray:
-    """phi on nodes -1..nx, -1..ny as an (nx+2, ny+2) array."""
+def potential(q: np.ndarray, scale: float, grid, solver: str = "open") -> np.ndarray:
+    """phi on nodes -1..nx, -1..ny as an (nx+2, ny+2) array: the open-boundary
+    convolution (solver="open") or the grounded pipe with walls through node 0
+    and node n of each axis (solver="pipe")."""
     nx, ny = int(grid["nx"]), int(grid["ny"])
     q = np.ascontiguousarray(q, dtype=np.int64)
     phi = np.zeros((nx + 2) * (ny + 2), dtype=np.float64)
-    lib().orc_potential(_ptr(q), float(scale), nx, ny, float(grid["dx"]), float(grid["dy"]),
-                        _ptr(phi))
+    fn = {"open": lib().orc_potential, "pipe": lib().orc_potential_pipe}[solver]
+    fn(_ptr(q), float(scale), nx, ny, float(grid["dx"]), float(grid["dy"]), _ptr(phi))
     return phi.reshape(nx + 2, ny + 2)
 
 
@@ -154,9 +160,9 @@ def field(phi: np.ndarray, grid) -> tuple[np.ndarray, np.ndarray]:
     return ex, ey
 
 
-def solve(q: np.ndarray, scale: float, grid) -> tuple[np.ndarray, np.ndarray]:
+def solve(q: np.ndarray, scale: float, grid, solver: str = "open") -> tuple[np.ndarray, np.ndarray]:
     """Field on the nodes from a charge grid: potential then centred differences."""
-    return field(potential(q, scale, grid), grid)
+    return field(potential(q, scale, grid, solver), grid)
 
 
 def _weights(parts):
@@ -179,7 +185,7 @@ def kick(parts: dict, grid, ex: np.ndarray, ey: np.ndarray, kappa: float) -> Non
                    _ptr(ey), float(kappa))
 
 
-def space_charge(parts: dict, grid, scale: float, kappa: float):
+def space_charge(parts: dict, grid, scale: float, kappa: float, solver: str = "open"):
     """One full space-charge step in place; returns (ex, ey, n_in)."""
     nx, ny = int(grid["nx"]), int(grid["ny"])
     ex = np.zeros(nx * ny)
@@ -188,14 +194,18 @@ def space_charge(parts: dict, grid, scale: float, kappa: float):
     n_in = lib().orc_space_charge(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
                                   _ptr(parts["py"]), _ptr(parts.get("lost")),
                                   _ptr(_weights(parts)), *_grid_args(grid), float(scale),
-                                  float(kappa), _ptr(ex), _ptr(ey))
+                                  float(kappa), _ptr(ex), _ptr(ey), _pipe(solver))
     return ex, ey, int(n_in)
 
 
-def track(parts: dict, grid, elements, n_turns: int) -> None:
+def _pipe(solver: str) -> int:
+    return {"open": 0, "pipe": 1}[solver]
+
+
+def track(parts: dict, grid, elements, n_turns: int, solver: str = "open") -> None:
     """In place: n_turns through the one-turn element sequence."""
     kind, par = _elements(elements)
     n = parts["x"].shape[0]
     lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
                     _ptr(parts.get("lost")), _ptr(_weights(parts)), *_grid_args(grid), len(kind),
-                    _ptr(kind), _ptr(par), int(n_turns))
+                    _ptr(kind), _ptr(par), int(n_turns), _pipe(solver))

@@ -244,6 +244,82 @@ void orc_potential(const int64_t *q, double scale, int nx, int ny, double dx, do
     free(G);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Grounded rectangular pipe (Sec. IV-B): the 5-point discrete Poisson       */
+/* equation with u = 0 on the walls.                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Potential in a grounded rectangular pipe whose walls pass through node 0
+ * and node nx along x (node nx is one spacing past the last grid node), and
+ * through node 0 and node ny along y.  phi solves, at every interior node
+ * (1 <= i <= nx-1, 1 <= j <= ny-1),
+ *   (phi[i-1][j] - 2 phi[i][j] + phi[i+1][j]) / dx^2
+ *     + (phi[i][j-1] - 2 phi[i][j] + phi[i][j+1]) / dy^2 = -2 pi rho[i][j] / (dx dy),
+ * with phi = 0 on the walls (the charge of the wall nodes i = 0 or j = 0 is
+ * taken by the grounded wall) -- the same normalisation as the open-boundary
+ * solve (lap G = -2 pi delta per unit charge).  The solution is written out as
+ * its expansion in the eigenvectors sin(p pi i / nx) sin(q pi j / ny) of the
+ * discrete Laplacian (eigenvalue -4 (sin^2(p pi/(2 nx))/dx^2 +
+ * sin^2(q pi/(2 ny))/dy^2)), summed separably in long double.  Output layout
+ * as orc_potential: nodes -1..nx by -1..ny, with the walls 0 and node -1 the
+ * mirror image -phi[1] (the odd extension across the wall at node 0). */
+void orc_potential_pipe(const int64_t *q, double scale, int nx, int ny, double dx, double dy,
+                        double *phi)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    int mi = nx - 1, mj = ny - 1; /* interior nodes per axis */
+    long double *sx = (long double *)malloc(sizeof(long double) * (size_t)nx * nx);
+    long double *sy = (long double *)malloc(sizeof(long double) * (size_t)ny * ny);
+    long double *a = (long double *)calloc((size_t)nx * ny, sizeof(long double));
+    long double *b = (long double *)calloc((size_t)nx * ny, sizeof(long double));
+    for (int p = 0; p < nx; ++p)
+        for (int i = 0; i < nx; ++i) sx[p * nx + i] = sinl(pi * p * i / nx);
+    for (int r = 0; r < ny; ++r)
+        for (int j = 0; j < ny; ++j) sy[r * ny + j] = sinl(pi * r * j / ny);
+    /* forward: f_hat[p][r] = sum_ij f[i][j] sin(p pi i/nx) sin(r pi j/ny) */
+    for (int i = 1; i <= mi; ++i)
+        for (int r = 1; r <= mj; ++r) {
+            long double s = 0.0L;
+            for (int j = 1; j <= mj; ++j) {
+                long double f = -2.0L * pi * ((long double)q[(int64_t)i * ny + j] * scale) /
+                                ((long double)dx * dy);
+                s += f * sy[r * ny + j];
+            }
+            a[i * ny + r] = s;
+        }
+    for (int p = 1; p <= mi; ++p)
+        for (int r = 1; r <= mj; ++r) {
+            long double s = 0.0L;
+            for (int i = 1; i <= mi; ++i) s += a[i * ny + r] * sx[p * nx + i];
+            long double spx = sinl(pi * p / (2.0L * nx)), spy = sinl(pi * r / (2.0L * ny));
+            long double lam = -4.0L * (spx * spx / ((long double)dx * dx) +
+                                       spy * spy / ((long double)dy * dy));
+            b[p * ny + r] = s / lam;
+        }
+    /* inverse: phi[i][j] = (2/nx)(2/ny) sum_pr phi_hat[p][r] sin(..) sin(..) */
+    for (int p = 1; p <= mi; ++p)
+        for (int j = 1; j <= mj; ++j) {
+            long double s = 0.0L;
+            for (int r = 1; r <= mj; ++r) s += b[p * ny + r] * sy[r * ny + j];
+            a[p * ny + j] = s;
+        }
+    int sy2 = ny + 2;
+    memset(phi, 0, sizeof(double) * (size_t)(nx + 2) * sy2);
+    for (int i = 1; i <= mi; ++i)
+        for (int j = 1; j <= mj; ++j) {
+            long double s = 0.0L;
+            for (int p = 1; p <= mi; ++p) s += a[p * ny + j] * sx[p * nx + i];
+            phi[(i + 1) * sy2 + (j + 1)] = (double)(s * 4.0L / ((long double)nx * ny));
+        }
+    /* odd images across the walls at node 0: node -1 mirrors node 1 */
+    for (int j = 0; j < ny + 2; ++j) phi[0 * sy2 + j] = -phi[2 * sy2 + j];
+    for (int i = 0; i < nx + 2; ++i) phi[i * sy2 + 0] = -phi[i * sy2 + 2];
+    free(sx);
+    free(sy);
+    free(a);
+    free(b);
+}
+
 /* E = -grad(phi) by centred differences at the nodes 0..nx-1, 0..ny-1. */
 void orc_field(const double *phi, int nx, int ny, double dx, double dy, double *ex, double *ey)
 {
@@ -291,13 +367,14 @@ void orc_kick(int64_t n, const double *x, double *px, const double *y, double *p
     }
 }
 
-/* The whole space-charge step at one location: deposit, potential, field,
- * kick.  scale converts charge units to the normalised density (1/(2^24 N0)
+/* The whole space-charge step at one location: deposit, potential (open
+ * boundary, or the grounded pipe when pipe != 0), field, kick.  scale converts charge units to the normalised density (1/(2^24 N0)
  * for N0 initial macro-particles, so the total charge is 1).  ex/ey, when not
  * NULL, receive the node field.  Returns the number of particles deposited. */
 int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
                          const float *wt, int nx, int ny, double x_min, double y_min, double dx,
-                         double dy, double scale, double kappa, double *ex_out, double *ey_out)
+                         double dy, double scale, double kappa, double *ex_out, double *ey_out,
+                         int pipe)
 {
     int64_t cells = (int64_t)nx * ny;
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)cells);
@@ -305,7 +382,10 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
     double *ex = ex_out ? ex_out : (double *)malloc(sizeof(double) * (size_t)cells);
     double *ey = ey_out ? ey_out : (double *)malloc(sizeof(double) * (size_t)cells);
     int64_t n_in = orc_deposit(n, x, y, lost, nx, ny, x_min, y_min, dx, dy, q);
-    orc_potential(q, scale, nx, ny, dx, dy, phi);
+    if (pipe)
+        orc_potential_pipe(q, scale, nx, ny, dx, dy, phi);
+    else
+        orc_potential(q, scale, nx, ny, dx, dy, phi);
     orc_field(phi, nx, ny, dx, dy, ex, ey);
     orc_kick(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
     if (!ex_out) free(ex);
@@ -321,14 +401,14 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
  * count, so lost particles take their charge with them. */
 void orc_track(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
                const float *wt, int nx, int ny, double x_min, double y_min, double dx, double dy,
-               int n_el, const int32_t *kind, const double *par, int n_turns)
+               int n_el, const int32_t *kind, const double *par, int n_turns, int pipe)
 {
     double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
     for (int t = 0; t < n_turns; ++t)
         for (int e = 0; e < n_el; ++e) {
             if (kind[e] == ORC_SC)
                 orc_space_charge(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale,
-                                 par[16 * e], NULL, NULL);
+                                 par[16 * e], NULL, NULL, pipe);
             else
                 orc_push(n, x, px, y, py, lost, 1, kind + e, par + 16 * e);
         }

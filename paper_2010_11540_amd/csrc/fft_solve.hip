@@ -316,13 +316,20 @@ __global__ void __launch_bounds__(kRowThreads)
 // fit on a compute unit at once.
 constexpr int kBatchRowThreads = 256;
 
+// The batched grid kernels walk their lines (rows or columns of every beam)
+// with a grid stride: a bounded number of workgroups per compute unit, each
+// taking line r, r + gridDim.x, ... (one line at a time, its beam uniform
+// over the workgroup), instead of one small workgroup per line.
 template <typename T>
-__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b)
+__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b, int rows)
 {
-    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
-    rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
-                                             I.my, I.log2_my, (const cx<T> *)I.tw_y,
-                                             (cx<T> *)I.spec_a, (int)blockIdx.x - I.row_block0);
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const BatchInstance &I = b.inst[b.row_inst[r]];
+        rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx,
+                                                 I.ny, I.my, I.log2_my, (const cx<T> *)I.tw_y,
+                                                 (cx<T> *)I.spec_a, r - I.row_block0);
+        __syncthreads();  // the next line reuses the LDS
+    }
 }
 
 // Column l of the row spectra: forward FFT along x, times the Green's
@@ -398,12 +405,15 @@ __global__ void __launch_bounds__(kColThreads)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
+__global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b, int cols)
 {
-    const BatchInstance &I = b.inst[b.col_inst[blockIdx.x]];
-    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
-                 (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
-                 (cx<T> *)I.spec_by, (int)blockIdx.x - I.col_block0);
+    for (int r = blockIdx.x; r < cols; r += gridDim.x) {
+        const BatchInstance &I = b.inst[b.col_inst[r]];
+        cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
+                     (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
+                     (cx<T> *)I.spec_by, r - I.col_block0);
+        __syncthreads();
+    }
 }
 
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
@@ -474,12 +484,15 @@ __global__ void __launch_bounds__(kInvThreads)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
+__global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b, int rows)
 {
-    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
-    rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
-                     I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
-                     (int)blockIdx.x - I.row_block0);
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const BatchInstance &I = b.inst[b.row_inst[r]];
+        rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
+                         I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
+                         r - I.row_block0);
+        __syncthreads();
+    }
 }
 
 template <typename T>
@@ -514,32 +527,41 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
     return launch_tail<T>(s, w, ex, ey, ef);
 }
 
+// Workgroups of a grid-stride batched launch: `per_cu` per compute unit, no
+// more than there are lines.
+int stride_grid(int lines, int n_cu, int per_cu) { return std::max(1, std::min(lines, n_cu * per_cu)); }
+
 template <typename T>
 hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows, int cols,
-                                  int max_nx, int max_ny, int max_pass_blocks)
+                                  int max_nx, int max_ny, int max_pass_blocks, int n_cu)
 {
     const int mmx = 2 * max_nx, mmy = 2 * max_ny;
     const size_t row_lds = rows_fwd_hdr_offset<T>(max_ny, mmy) +
                            sizeof(BlockHeader) * (size_t)std::max(max_pass_blocks, 1);
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
     const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)mmy;
-    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kBatchRowThreads), row_lds, s, b);
+    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(stride_grid(rows, n_cu, 8)),
+                       dim3(kBatchRowThreads), row_lds, s, b, rows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cols_batched<T>, dim3(cols), dim3(kColThreads), col_lds, s, b);
+    hipLaunchKernelGGL(k_cols_batched<T>, dim3(stride_grid(cols, n_cu, 8)), dim3(kColThreads),
+                       col_lds, s, b, cols);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_inv_batched<T>, dim3(rows), dim3(kInvThreads), inv_lds, s, b);
+    hipLaunchKernelGGL(k_rows_inv_batched<T>, dim3(stride_grid(rows, n_cu, 16)),
+                       dim3(kInvThreads), inv_lds, s, b, rows);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny, int max_pass_blocks)
+                                int cols, int max_nx, int max_ny, int max_pass_blocks, int n_cu)
 {
-    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks)
-                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks);
+    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks,
+                                                 n_cu)
+                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny,
+                                                  max_pass_blocks, n_cu);
 }
 
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,
