@@ -50,6 +50,8 @@ def parse():
                     help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
                          "bunch with line-density kick weights, 256^2; batch: 64-beam tune scan")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--solver", default="open", choices=["open", "pipe"],
+                    help="open-boundary convolution, or the grounded rectangular pipe")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
     ap.add_argument("--pass-threads", type=int, default=0)
     ap.add_argument("--pass-blocks", type=int, default=0)
@@ -92,7 +94,7 @@ def measured_traffic(n_particles: int):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds: float):
+def cpu_baseline(w, seconds: float, solver: str = "open"):
     """The oracle on the host cores: the production lattice's first space-charge
     steps on the full beam, repeated until `seconds` of wall time."""
     import numpy as np
@@ -109,7 +111,7 @@ def cpu_baseline(w, seconds: float):
     steps = 0
     t0 = time.perf_counter()
     while True:
-        oracle.track(parts, w["grid"], chunk, 1)
+        oracle.track(parts, w["grid"], chunk, 1, solver=solver)
         steps += chunk_steps
         el = time.perf_counter() - t0
         if el >= seconds:
@@ -274,6 +276,8 @@ def main():
         sys.exit(2)
     n = w["n"]
     ctx = scpic.Context(w["grid"], args.precision)
+    if args.solver == "pipe":
+        ctx.set_option(scpic.OPT_SOLVER, scpic.SOLVER_PIPE)
     if args.no_graph:
         ctx.set_option(scpic.OPT_USE_GRAPH, 0)
     if args.pass_threads:
@@ -352,7 +356,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds, args.solver)
 
     out = {
         "metric": "particle-steps/s (push+deposit+solve+kick)",
@@ -373,6 +377,7 @@ def main():
             "grid": f"{w['grid']['nx']}x{w['grid']['ny']}",
             "sc_steps_per_turn": steps_per_turn,
             "precision": args.precision,
+            "solver": args.solver,
             "graph": not args.no_graph,
             "alive_after": alive,
             "gpu_event_ms": round(gpu_ms, 3),

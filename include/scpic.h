@@ -186,10 +186,27 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
  *                            one per compute unit).
  *   SCPIC_OPT_PASS_THREADS   threads per workgroup of the particle pass
  *                            (256, 512 or 1024; default 1024).
+ *   SCPIC_OPT_SOLVER         SCPIC_SOLVER_OPEN (default): the open-boundary
+ *                            convolution of scpic_solve's comment;
+ *                            SCPIC_SOLVER_PIPE: the grounded rectangular pipe
+ *                            of Sec. IV-B -- the 5-point discrete Poisson
+ *                            equation lap phi = -2 pi rho / (dx dy) with
+ *                            phi = 0 on walls through node 0 and node nx along
+ *                            x (node nx is one spacing past the last node),
+ *                            and node 0 and node ny along y; the charge on the
+ *                            wall nodes i = 0 or j = 0 goes to the wall.
+ *                            Solved by the paper's odd extension and DFT,
+ *                            each mode divided by the Laplacian's eigenvalue.
+ *                            Applies to scpic_solve, scpic_track and
+ *                            scpic_reduce_solve; waits for the context's
+ *                            stream and drops its cached turn graphs.
  * Results do not depend on the launch shape. */
 #define SCPIC_OPT_USE_GRAPH 1
 #define SCPIC_OPT_PASS_BLOCKS 2
 #define SCPIC_OPT_PASS_THREADS 3
+#define SCPIC_OPT_SOLVER 4
+#define SCPIC_SOLVER_OPEN 0
+#define SCPIC_SOLVER_PIPE 1
 scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value);
 
 /* Fused particle pass, one launch: optionally kick with the context's

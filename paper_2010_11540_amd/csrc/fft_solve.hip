@@ -259,7 +259,7 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
                                               const int64_t *__restrict__ q, double scale, int nx,
                                               int ny, int my, int log2my,
                                               const cx<T> *__restrict__ tw, cx<T> *__restrict__ at,
-                                              int i)
+                                              int i, bool pipe)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // my entries
@@ -287,9 +287,16 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
         if (tid < ny) rho[tid] = (T)((double)qv * scale);
     }
     __syncthreads();
+    // the row as a real sequence of length my: zero-padded (open boundary),
+    // or odd-extended about the walls at j = 0 and j = ny (grounded pipe; the
+    // wall row i = 0 and the wall column j = 0 take no charge)
+    auto sample = [&](int l) -> T {
+        if (!pipe) return l < ny ? rho[l] : T(0);
+        if (i == 0 || l == 0 || l == ny) return T(0);
+        return l < ny ? rho[l] : -rho[my - l];
+    };
     const int half = ny;  // complex length: my / 2
-    if (tid < half)
-        a[tid] = (2 * tid + 1 < ny) ? cx<T>{rho[2 * tid], rho[2 * tid + 1]} : cx<T>{T(0), T(0)};
+    if (tid < half) a[tid] = cx<T>{sample(2 * tid), sample(2 * tid + 1)};
     const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, NT);
     for (int l = tid; l <= ny; l += NT) {
         const cx<T> zl = Z[l & (half - 1)];
@@ -304,10 +311,10 @@ template <typename T, bool FROM_PARTIALS>
 __global__ void __launch_bounds__(kRowThreads)
     k_rows_fwd(DepositTarget dep, int nblocks, const int64_t *__restrict__ q, double scale,
                int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
-               cx<T> *__restrict__ at)
+               cx<T> *__restrict__ at, bool pipe)
 {
     rows_fwd_body<T, FROM_PARTIALS, kRowThreads>(dep, nblocks, q, scale, nx, ny, my, log2my, tw,
-                                                 at, (int)blockIdx.x);
+                                                 at, (int)blockIdx.x, pipe);
 }
 
 // Every beam of a batch: workgroup -> (beam, row) from the batch's row table;
@@ -327,7 +334,7 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
         const BatchInstance &I = b.inst[b.row_inst[r]];
         rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx,
                                                  I.ny, I.my, I.log2_my, (const cx<T> *)I.tw_y,
-                                                 (cx<T> *)I.spec_a, r - I.row_block0);
+                                                 (cx<T> *)I.spec_a, r - I.row_block0, false);
         __syncthreads();  // the next line reuses the LDS
     }
 }
@@ -339,7 +346,7 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
                                           int log2mx, const cx<T> *__restrict__ tw,
                                           const T *__restrict__ ghat_t, const T *__restrict__ sx,
                                           const T *__restrict__ sy, cx<T> *__restrict__ bx,
-                                          cx<T> *__restrict__ by, int l)
+                                          cx<T> *__restrict__ by, int l, bool pipe)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
@@ -360,7 +367,12 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
         vt[r] = k < mx ? tw[k] : cx<T>{T(0), T(0)};
         vg[r] = k < mx ? g[k] : T(0);
         vs[r] = k < mx ? sx[k] : T(0);
-        va[r] = k < nx ? col[k] : cx<T>{T(0), T(0)};
+        // zero-padded column (open boundary), or its odd extension about
+        // the walls at i = 0 and i = nx (grounded pipe)
+        const int src = k < nx ? k : mx - k;
+        const bool zero = pipe ? (k == 0 || k == nx) : k >= nx;
+        const cx<T> c = zero ? cx<T>{T(0), T(0)} : col[src];
+        va[r] = (pipe && k > nx) ? cx<T>{-c.re, -c.im} : c;
     }
     const T syl = sy[l];
 #pragma unroll
@@ -399,9 +411,9 @@ template <typename T>
 __global__ void __launch_bounds__(kColThreads)
     k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
            const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
-           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by)
+           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by, bool pipe)
 {
-    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x);
+    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x, pipe);
 }
 
 template <typename T>
@@ -411,7 +423,7 @@ __global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b, int
         const BatchInstance &I = b.inst[b.col_inst[r]];
         cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
                      (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
-                     (cx<T> *)I.spec_by, r - I.col_block0);
+                     (cx<T> *)I.spec_by, r - I.col_block0, false);
         __syncthreads();
     }
 }
@@ -503,7 +515,7 @@ hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *e
     hipLaunchKernelGGL(k_cols<T>, dim3(w.ny + 1), dim3(kColThreads), col_lds, s,
                        (const cx<T> *)w.spec_a, w.nx, w.ny, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
                        (const T *)w.ghat_t, (const T *)w.sx, (const T *)w.sy, (cx<T> *)w.spec_bx,
-                       (cx<T> *)w.spec_by);
+                       (cx<T> *)w.spec_by, w.pipe);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kInvThreads), inv_lds, s,
@@ -521,7 +533,7 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
                            (FROM_PARTIALS ? sizeof(BlockHeader) * (size_t)std::max(nblocks, 1) : 0);
     hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx), dim3(kRowThreads), row_lds, s,
                        dep, nblocks, q, scale, w.nx, w.ny, w.my, w.log2_my,
-                       (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a);
+                       (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a, w.pipe);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tail<T>(s, w, ex, ey, ef);

@@ -388,19 +388,43 @@ void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t)
         }
 }
 
+// Grounded rectangular pipe (walls through node 0 and node n of each axis):
+// the odd extension of the charge is 2nx x 2ny periodic, and the 5-point
+// Laplacian acts on its DFT mode (k, l) as multiplication by
+//   lambda = -4 (sin^2(pi k / mx) / dx^2 + sin^2(pi l / my) / dy^2).
+// With the open-boundary solve's normalisation (lap phi = -2 pi rho per unit
+// area) the potential's spectrum is -2 pi rho^ / (dx dy lambda); mode (0, 0)
+// is zero (the odd extension has no mean).  Divided by mx*my like ghat_t.
+void pipe_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t)
+{
+    const int mx = 2 * nx, my = 2 * ny;
+    const double norm = 1.0 / ((double)mx * (double)my);
+    for (int l = 0; l <= ny; ++l)
+        for (int k = 0; k < mx; ++k) {
+            const double sk = std::sin(M_PI * k / mx), sl = std::sin(M_PI * l / my);
+            const double lam = -4.0 * (sk * sk / (dx * dx) + sl * sl / (dy * dy));
+            ghat_t[(size_t)l * mx + k] =
+                (k == 0 && l == 0) ? 0.0 : (-2.0 * M_PI / (dx * dy)) / lam * norm;
+        }
+}
+
 }  // namespace scpic
 
 namespace {
 
-// Green's spectrum, twiddles and difference factors of a grid, converted to
-// T and copied to the given device tables.
+// Green's spectrum (open boundary) or the pipe's mode divisors, twiddles and
+// difference factors of a grid, converted to T and copied to the given
+// device tables.
 template <typename T>
 scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x, void *tw_y,
-                                void *sx_t, void *sy_t)
+                                void *sx_t, void *sy_t, bool pipe = false)
 {
     const int nx = grid.nx, ny = grid.ny, mx = 2 * nx, my = 2 * ny;
     std::vector<double> ghat((size_t)(ny + 1) * mx);
-    green_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
+    if (pipe)
+        pipe_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
+    else
+        green_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
     std::vector<T> g_t(ghat.size()), twx(2 * (size_t)mx), twy(2 * (size_t)my), sx(mx), sy(ny + 1);
     for (size_t i = 0; i < ghat.size(); ++i) g_t[i] = (T)ghat[i];
     for (int t = 0; t < mx; ++t) {
@@ -425,7 +449,7 @@ template <typename T>
 scpic_status upload_tables(scpic_ctx *c)
 {
     return upload_grid_tables<T>(c->grid, c->sw.ghat_t, c->sw.tw_x, c->sw.tw_y, c->sw.sx,
-                                 c->sw.sy);
+                                 c->sw.sy, c->sw.pipe);
 }
 
 scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision, void *stream)
@@ -467,6 +491,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     c->sw.log2_mx = ilog2(2 * nx);
     c->sw.log2_my = ilog2(2 * ny);
     c->sw.mixed = c->mixed;
+    c->sw.pipe = false;
     ALLOC(c->sw.tw_x, ce * 2 * nx);
     ALLOC(c->sw.tw_y, ce * 2 * ny);
     ALLOC(c->sw.ghat_t, fe * (size_t)(ny + 1) * 2 * nx);
@@ -551,6 +576,19 @@ scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
             return fail(SCPIC_EINVAL, "pass blocks must be in [0, " + std::to_string(ctx->max_blocks) + "]");
         ctx->pass_blocks = (int)value;
         return SCPIC_OK;
+    case SCPIC_OPT_SOLVER: {
+        if (value != SCPIC_SOLVER_OPEN && value != SCPIC_SOLVER_PIPE)
+            return fail(SCPIC_EINVAL, "solver must be SCPIC_SOLVER_OPEN or SCPIC_SOLVER_PIPE");
+        const bool pipe = value == SCPIC_SOLVER_PIPE;
+        if (pipe == ctx->sw.pipe) return SCPIC_OK;
+        // captured turns carry the solver: drop them once queued work is done
+        SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        for (auto &g : ctx->graphs)
+            if (g.exec) hipGraphExecDestroy(g.exec);
+        ctx->graphs.clear();
+        ctx->sw.pipe = pipe;
+        return ctx->mixed ? upload_tables<float>(ctx) : upload_tables<double>(ctx);
+    }
     case SCPIC_OPT_PASS_THREADS:
         if (value != 256 && value != 512 && value != 1024)
             return fail(SCPIC_EINVAL, "pass threads must be 256, 512 or 1024");

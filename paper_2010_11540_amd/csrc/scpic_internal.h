@@ -127,6 +127,7 @@ hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_use
 struct SolveWorkspace {
     int nx, ny, mx, my, log2_mx, log2_my;
     bool mixed;
+    bool pipe;           // grounded rectangular pipe instead of the open boundary
     void *tw_x, *tw_y;   // [mx], [my] complex twiddles exp(-2 pi i t / m)
     void *ghat_t;        // [ny+1][mx] real Green's spectrum / (mx my), transposed
     void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [ny+1] sin(2 pi l / my)/dy
@@ -154,5 +155,10 @@ hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed,
 // Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
 // the padded 2nx x 2ny periodic kernel.
 void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t);
+
+// The grounded pipe's counterpart of ghat_t (same layout and normalisation):
+// the inverse of the 5-point Laplacian's eigenvalue per mode of the odd
+// extension, times -2 pi / (dx dy), mode (0, 0) zero.
+void pipe_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t);
 
 }  // namespace scpic

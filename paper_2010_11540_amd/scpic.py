@@ -23,7 +23,8 @@ _LIB_PATH = Path(__file__).resolve().parent / "libscpic.so"
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
-OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS = 1, 2, 3
+OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS, OPT_SOLVER = 1, 2, 3, 4
+SOLVER_OPEN, SOLVER_PIPE = 0, 1
 
 # every function the header declares, for load checks
 EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",

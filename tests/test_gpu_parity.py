@@ -176,6 +176,25 @@ def test_solve_matches_oracle(gpu, orc, nx, ny, hx, hy, precision, tol):
     assert _field_err(ey, ey_ref) <= tol, _field_err(ey, ey_ref)
 
 
+@pytest.mark.parametrize("nx,ny,hx,hy", [(32, 16, 4e-3, 3e-3), (64, 64, 6e-3, 6e-3),
+                                         (128, 128, 6e-3, 6e-3), (16, 128, 5e-3, 7e-3),
+                                         (256, 256, 12e-3, 6e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_pipe_solve_matches_oracle(gpu, orc, nx, ny, hx, hy, precision, tol):
+    _say(f"pipe solve {precision} grid={nx}x{ny}")
+    g = inputs.make_grid(nx, ny, hx, hy)
+    q, scale = _charge(50_000, 17, g, orc)
+    ex_ref, ey_ref = orc.solve(q, scale, g, "pipe")
+    import torch
+    with gpu.Context(g, precision) as ctx:
+        ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_PIPE)
+        ex, ey = ctx.solve(torch.from_numpy(q).cuda(), scale)
+        ex = ex.double().cpu().numpy()
+        ey = ey.double().cpu().numpy()
+    assert _field_err(ex, ex_ref) <= tol, _field_err(ex, ex_ref)
+    assert _field_err(ey, ey_ref) <= tol, _field_err(ey, ey_ref)
+
+
 def test_solve_zero_charge_gives_zero_field(gpu):
     _say("solve zero charge")
     import torch
@@ -234,6 +253,36 @@ def test_small_workload_one_turn_fp64(gpu, orc, use_graph):
         h = _host(d)
     np.testing.assert_array_equal(h["lost"], ref["lost"])
     assert _turn_err(h, ref) <= 1e-10, _turn_err(h, ref)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_small_workload_one_turn_pipe_fp64(gpu, orc, use_graph):
+    """The small workload in a grounded pipe (walls at the grid's first node
+    and one spacing past its last) against the oracle; switching back to the
+    open boundary then reproduces the open-boundary turn."""
+    _say(f"track small workload 1 turn, grounded pipe, graph={use_graph}")
+    w = inputs.workload("small")
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, w["grid"], w["lattice"], 1, solver="pipe")
+    ref_open = inputs.copy_parts(w["parts"])
+    orc.track(ref_open, w["grid"], w["lattice"], 1)
+    with gpu.Context(w["grid"]) as ctx:
+        ctx.set_option(gpu.OPT_USE_GRAPH, int(use_graph))
+        d = _dev(w["parts"])
+        ctx.track(d, w["lattice"], 1)  # open boundary first: caches its turn
+        ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_PIPE)
+        d = _dev(w["parts"])
+        ctx.track(d, w["lattice"], 1)
+        h = _host(d)
+        ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_OPEN)
+        d = _dev(w["parts"])
+        ctx.track(d, w["lattice"], 1)
+        h_open = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    assert _turn_err(h, ref) <= 1e-10, _turn_err(h, ref)
+    assert _turn_err(h_open, ref_open) <= 1e-10, _turn_err(h_open, ref_open)
+    # the walls change the answer
+    assert _turn_err(h, ref_open) > 1e-6
 
 
 def test_small_workload_three_turns_graph_equals_direct(gpu, orc):
