@@ -145,61 +145,42 @@ __device__ __forceinline__ RowLanes row_lanes(int ny, int tid)
     return r;
 }
 
-// The lane's first round of partial loads (workgroups grp + u * groups,
-// u < kReduceChunk).  Every slice address is valid whatever the headers say
-// (workgroups past nblocks read slice 0), so these loads can go out with the
-// headers' loads, before the headers are known; chunks outside a workgroup's
-// box are masked afterwards.
-template <int NT>
-__device__ __forceinline__ void prefetch_row(const DepositTarget &dep, int nblocks, int i, int ny,
-                                             int tid, uint4 (&v)[kReduceChunk])
-{
-    const RowLanes L = row_lanes<NT>(ny, tid);
-    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + L.j0c;
-#pragma unroll
-    for (int u = 0; u < kReduceChunk; ++u) {
-        const int b = L.grp + u * L.groups;
-        v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(b < nblocks ? b : 0) * ny);
-    }
-}
-
 template <int NT>
 __device__ __forceinline__ unsigned long long reduce_row(const DepositTarget &dep,
                                                          const BlockHeader *hdr,
                                                          unsigned long long *red, int nblocks,
                                                          int i, int ny, int tid,
-                                                         unsigned long long carry_v,
-                                                         const uint4 (&first)[kReduceChunk])
+                                                         unsigned long long carry_v)
 {
     const RowLanes L = row_lanes<NT>(ny, tid);
     const int groups = L.groups, grp = L.grp, j0c = L.j0c;
     unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    // add the chunks of workgroups b0 + u * groups that fall inside their box
-    auto add = [&](const uint4 (&v)[kReduceChunk], int b0) {
+    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
+    for (int b0 = grp; b0 < nblocks; b0 += groups * kReduceChunk) {
+        uint4 v[kReduceChunk];
+        int lo[kReduceChunk], hi[kReduceChunk];
+        // Branch-free: every lane issues its loads back to back (a chunk
+        // outside a workgroup's box is read from workgroup 0's slice, always
+        // valid and usually cached, and masked), so the compiler does not
+        // wait between them.
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
             const int b = b0 + u * groups;
-            const BlockHeader h = hdr[b < nblocks ? b : 0];
+            const int bc = b < nblocks ? b : 0;
+            const BlockHeader h = hdr[bc];
             const bool take = b < nblocks && i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 &&
                               j0c <= h.j1;
-            const int lo = take ? h.j0 : 0, hi = take ? h.j1 : -1;
-            s0 += (j0c + 0 >= lo && j0c + 0 <= hi) ? v[u].x : 0u;
-            s1 += (j0c + 1 >= lo && j0c + 1 <= hi) ? v[u].y : 0u;
-            s2 += (j0c + 2 >= lo && j0c + 2 <= hi) ? v[u].z : 0u;
-            s3 += (j0c + 3 >= lo && j0c + 3 <= hi) ? v[u].w : 0u;
+            lo[u] = take ? h.j0 : 0;
+            hi[u] = take ? h.j1 : -1;
+            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(take ? bc : 0) * ny);
         }
-    };
-    add(first, grp);
-    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
-    for (int b0 = grp + groups * kReduceChunk; b0 < nblocks; b0 += groups * kReduceChunk) {
-        // branch-free: workgroups past nblocks read slice 0 (valid, masked)
-        uint4 v[kReduceChunk];
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
-            const int b = b0 + u * groups;
-            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(b < nblocks ? b : 0) * ny);
+            s0 += (j0c + 0 >= lo[u] && j0c + 0 <= hi[u]) ? v[u].x : 0u;
+            s1 += (j0c + 1 >= lo[u] && j0c + 1 <= hi[u]) ? v[u].y : 0u;
+            s2 += (j0c + 2 >= lo[u] && j0c + 2 <= hi[u]) ? v[u].z : 0u;
+            s3 += (j0c + 3 >= lo[u] && j0c + 3 <= hi[u]) ? v[u].w : 0u;
         }
-        add(v, b0);
     }
     unsigned long long *mine = red + (size_t)grp * ny + j0c;
     mine[0] = s0;
@@ -225,12 +206,9 @@ __global__ void __launch_bounds__(kRowThreads)
     __shared__ unsigned long long red[kRowThreads * 4];
     const int tid = threadIdx.x, i = blockIdx.x;
     const unsigned long long cv = tid < ny ? dep.carry[(size_t)i * ny + tid] : 0ull;
-    uint4 first[kReduceChunk];
-    prefetch_row<kRowThreads>(dep, nblocks, i, ny, tid, first);
     for (int b = tid; b < nblocks; b += kRowThreads) hdr[b] = dep.header[b];
     __syncthreads();
-    const unsigned long long t =
-        reduce_row<kRowThreads>(dep, hdr, red, nblocks, i, ny, tid, cv, first);
+    const unsigned long long t = reduce_row<kRowThreads>(dep, hdr, red, nblocks, i, ny, tid, cv);
     if (tid < ny) q[(size_t)i * ny + tid] = (int64_t)t;
     if (n_in != nullptr && i == 0 && tid < 64) {
         long long cnt = 0;
@@ -273,15 +251,12 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
     const int64_t qv = (!FROM_PARTIALS && tid < ny) ? q[(size_t)i * ny + tid] : 0;
     const unsigned long long cv =
         (FROM_PARTIALS && tid < ny) ? dep.carry[(size_t)i * ny + tid] : 0ull;
-    uint4 first[kReduceChunk];
-    if (FROM_PARTIALS) prefetch_row<NT>(dep, nblocks, i, ny, tid, first);
     for (int t = tid; t < my; t += NT) twl[t] = tw[t];
     if (FROM_PARTIALS)
         for (int t = tid; t < nblocks; t += NT) hdr[t] = dep.header[t];
     if (FROM_PARTIALS) {
         __syncthreads();
-        const unsigned long long t =
-            reduce_row<NT>(dep, hdr, red, nblocks, i, ny, tid, cv, first);
+        const unsigned long long t = reduce_row<NT>(dep, hdr, red, nblocks, i, ny, tid, cv);
         if (tid < ny) rho[tid] = (T)((double)t * scale);
     } else {
         if (tid < ny) rho[tid] = (T)((double)qv * scale);
@@ -323,20 +298,14 @@ __global__ void __launch_bounds__(kRowThreads)
 // fit on a compute unit at once.
 constexpr int kBatchRowThreads = 256;
 
-// The batched grid kernels walk their lines (rows or columns of every beam)
-// with a grid stride: a bounded number of workgroups per compute unit, each
-// taking line r, r + gridDim.x, ... (one line at a time, its beam uniform
-// over the workgroup), instead of one small workgroup per line.
 template <typename T>
-__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b, int rows)
+__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b)
 {
-    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-        const BatchInstance &I = b.inst[b.row_inst[r]];
-        rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx,
-                                                 I.ny, I.my, I.log2_my, (const cx<T> *)I.tw_y,
-                                                 (cx<T> *)I.spec_a, r - I.row_block0, false);
-        __syncthreads();  // the next line reuses the LDS
-    }
+    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
+    rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
+                                             I.my, I.log2_my, (const cx<T> *)I.tw_y,
+                                             (cx<T> *)I.spec_a, (int)blockIdx.x - I.row_block0,
+                                             false);
 }
 
 // Column l of the row spectra: forward FFT along x, times the Green's
@@ -417,15 +386,12 @@ __global__ void __launch_bounds__(kColThreads)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b, int cols)
+__global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
 {
-    for (int r = blockIdx.x; r < cols; r += gridDim.x) {
-        const BatchInstance &I = b.inst[b.col_inst[r]];
-        cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
-                     (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
-                     (cx<T> *)I.spec_by, r - I.col_block0, false);
-        __syncthreads();
-    }
+    const BatchInstance &I = b.inst[b.col_inst[blockIdx.x]];
+    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
+                 (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
+                 (cx<T> *)I.spec_by, (int)blockIdx.x - I.col_block0, false);
 }
 
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
@@ -496,15 +462,12 @@ __global__ void __launch_bounds__(kInvThreads)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b, int rows)
+__global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
 {
-    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
-        const BatchInstance &I = b.inst[b.row_inst[r]];
-        rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
-                         I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
-                         r - I.row_block0);
-        __syncthreads();
-    }
+    const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
+    rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
+                     I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
+                     (int)blockIdx.x - I.row_block0);
 }
 
 template <typename T>
@@ -539,41 +502,33 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
     return launch_tail<T>(s, w, ex, ey, ef);
 }
 
-// Workgroups of a grid-stride batched launch: `per_cu` per compute unit, no
-// more than there are lines.
-int stride_grid(int lines, int n_cu, int per_cu) { return std::max(1, std::min(lines, n_cu * per_cu)); }
-
 template <typename T>
 hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows, int cols,
-                                  int max_nx, int max_ny, int max_pass_blocks, int n_cu)
+                                  int max_nx, int max_ny, int max_pass_blocks)
 {
     const int mmx = 2 * max_nx, mmy = 2 * max_ny;
     const size_t row_lds = rows_fwd_hdr_offset<T>(max_ny, mmy) +
                            sizeof(BlockHeader) * (size_t)std::max(max_pass_blocks, 1);
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
     const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)mmy;
-    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(stride_grid(rows, n_cu, 8)),
-                       dim3(kBatchRowThreads), row_lds, s, b, rows);
+    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kBatchRowThreads), row_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cols_batched<T>, dim3(stride_grid(cols, n_cu, 8)), dim3(kColThreads),
-                       col_lds, s, b, cols);
+    hipLaunchKernelGGL(k_cols_batched<T>, dim3(cols), dim3(kColThreads), col_lds, s, b);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_inv_batched<T>, dim3(stride_grid(rows, n_cu, 16)),
-                       dim3(kInvThreads), inv_lds, s, b, rows);
+    hipLaunchKernelGGL(k_rows_inv_batched<T>, dim3(rows), dim3(kInvThreads), inv_lds, s, b);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny, int max_pass_blocks, int n_cu)
+                                int cols, int max_nx, int max_ny, int max_pass_blocks)
 {
-    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks,
-                                                 n_cu)
+    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks)
                  : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny,
-                                                  max_pass_blocks, n_cu);
+                                                  max_pass_blocks);
 }
 
 hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_used, int nx, int ny,

@@ -1098,7 +1098,7 @@ scpic_status batch_enqueue(scpic_batch *b, hipStream_t s, const scpic_particles 
         if (e != hipSuccess) return fail_hip(e, "batched pass launch");
         if (op.deposit) {
             e = launch_solve_batched(s, b->launch, b->mixed, b->total_rows, b->total_cols,
-                                     b->max_nx, b->max_ny, b->max_beam_blocks, b->n_cu);
+                                     b->max_nx, b->max_ny, b->max_beam_blocks);
             if (e != hipSuccess) return fail_hip(e, "batched solve launch");
         }
     }

@@ -147,10 +147,9 @@ hipError_t launch_solve_partials(hipStream_t s, const SolveWorkspace &w, const D
 
 // Field of every beam of a batch from the partials of its last batched pass,
 // interleaved into each beam's ef: rows = sum of nx, cols = sum of (ny + 1);
-// max_pass_blocks bounds every beam's pass workgroups; n_cu sizes the
-// grid-stride launches.
+// max_pass_blocks bounds every beam's pass workgroups.
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny, int max_pass_blocks, int n_cu);
+                                int cols, int max_nx, int max_ny, int max_pass_blocks);
 
 // Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
 // the padded 2nx x 2ny periodic kernel.
