@@ -212,12 +212,13 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 //   DEPOSIT  add the particle's four weights to the workgroup's LDS tile of
 //            the charge grid (nodes outside the tile: global atomics on the
 //            carry grid); particles outside the domain are marked lost.
-// A workgroup owns the same particles at every step of a track, so the box
-// its previous deposit recorded (its header) holds every node its kick
-// gathers from: that box of the field is staged in LDS with coalesced loads
-// beside the charge tile when it fits, and gathers from outside it read
-// global memory.  At the end each workgroup writes the bounding box of its
-// tile cells to its slice of the partials (no global atomics).
+// When the whole charge grid fits in LDS it is the tile and gathers read the
+// L2-resident field.  Otherwise the tile covers the box the workgroup's
+// previous deposit recorded (its header; a workgroup owns the same particles
+// at every step of a track), and that box of the field, which holds every
+// node the kick gathers from, is staged in LDS beside the tile when it fits.
+// At the end each workgroup writes the bounding box of its tile cells to its
+// slice of the partials (no global atomics).
 // The body is shared by the single-beam kernel and the batched one: bid is
 // the workgroup's index among the nblk workgroups working on beam P (its
 // slice of the partials and its header), T = nblk * blockDim.x.
@@ -247,17 +248,23 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         if (KICK && P.w) wp = P.w[p];
     }
 
+    // When the whole charge grid fits in LDS it is the tile, and the kick
+    // gathers from the L2-resident field: the set-up then needs nothing from
+    // the previous pass (no header read, no field staging), only the zeroing
+    // of the tile.  Otherwise the previous pass's header sizes the tile and the
+    // staged field box.
+    const bool whole = DEPOSIT && (size_t)g.nx * g.ny <= lds_bytes / sizeof(uint32_t);
     BlockHeader hd;
     hd.i0 = -1;
     hd.i1 = -2;
     hd.j0 = -1;
     hd.j1 = -2;
-    if (KICK || DEPOSIT) hd = dep.header[bid];
+    if ((KICK || DEPOSIT) && !whole) hd = dep.header[bid];
     // LDS layout: [charge tile][staged field box + 2 nodes of slack]
     Box tile{0, 0, 0, 0};
     size_t tile_bytes = 0;
     if constexpr (DEPOSIT) {
-        tile = charge_tile(g, hd, lds_bytes);
+        tile = whole ? Box{0, 0, g.nx, g.ny} : charge_tile(g, hd, lds_bytes);
         tile_bytes = sizeof(uint32_t) * (size_t)tile.h * tile.w;
     }
     uint32_t *lq = reinterpret_cast<uint32_t *>(lds);
@@ -268,7 +275,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         const bool known = hd.i0 >= 0 && hd.i0 <= hd.i1 && hd.j0 >= 0 && hd.j0 <= hd.j1 &&
                            hd.i1 < g.nx && hd.j1 < g.ny;
         ebox = Box{hd.i0, hd.j0, hd.i1 - hd.i0 + 1, hd.j1 - hd.j0 + 1};
-        staged = known &&
+        staged = !whole && known &&
                  ((size_t)ebox.h * ebox.w + 2) * sizeof(V) + tile_bytes <= (size_t)lds_bytes;
         if (staged) {
             // four nodes per thread per round; indices past the box repeat
