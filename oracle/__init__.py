@@ -10,8 +10,11 @@ multiply-add, OpenMP over particles / target nodes).  This file only builds it
 with gcc and marshals numpy arrays through ctypes.
 
 What each function follows (arXiv:2010.11540):
-  push        Sec. III: transfer map per element, linear (v <- M v) or the kick
-              step of the split thick sextupole (Sec. III-C, potential V).
+  push        Sec. III: transfer map per element, linear (v <- M v), the kick
+              step of the split thick sextupole (Sec. III-C, potential V), the
+              chromatic thick quadrupole (Sec. III-B, closed form, with the
+              path-length integral for sigma) or the thick sextupole as the
+              symmetric five-flow product of Sec. III-C (eq. Sym2).
   deposit     Sec. IV-A: bilinear (cloud-in-cell) charge assignment to the four
               nodes of a cell, in 2^-24 fixed-point charge units.
   potential   open-boundary Poisson solve by convolution with the free-space
@@ -37,7 +40,7 @@ _HERE = Path(__file__).resolve().parent
 _SRC = _HERE / "scpic_oracle.c"
 _LIB = _HERE / "liborc.so"
 
-LIN2X2, LIN4X4, SEXT_THIN, SC = 1, 2, 3, 4
+LIN2X2, LIN4X4, SEXT_THIN, SC, QUAD_THICK, SEXT_THICK = 1, 2, 3, 4, 5, 6
 CHARGE_ONE = 1 << 24
 
 _C_FLAGS = ["-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -64,8 +67,8 @@ def lib():
         L = ctypes.CDLL(str(_LIB))
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         L.orc_num_threads.restype = i32
-        L.orc_push.argtypes = [i64, vp, vp, vp, vp, vp, i32, vp, vp]
-        L.orc_push.restype = None
+        L.orc_push.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
+        L.orc_push.restype = i32
         L.orc_deposit.argtypes = [i64, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp]
         L.orc_deposit.restype = i64
         L.orc_green.argtypes = [i32, i32, dbl, dbl]
@@ -82,9 +85,9 @@ def lib():
         L.orc_space_charge.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
                                        dbl, dbl, vp, vp, i32]
         L.orc_space_charge.restype = i64
-        L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, vp,
-                                vp, i32, i32]
-        L.orc_track.restype = None
+        L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
+                                i32, vp, vp, i32, i32]
+        L.orc_track.restype = i32
         _lib = L
     return _lib
 
@@ -113,12 +116,24 @@ def num_threads() -> int:
     return lib().orc_num_threads()
 
 
+def _longitudinal(parts):
+    s, ps = parts.get("sigma"), parts.get("psigma")
+    for a in (s, ps):
+        if a is not None and (a.dtype != np.float64 or not a.flags.c_contiguous):
+            raise TypeError("sigma and psigma must be contiguous float64 arrays")
+    return _ptr(s), _ptr(ps)
+
+
 def push(parts: dict, elements) -> None:
-    """In place: push particles through the non-space-charge elements."""
+    """In place: push particles through the non-space-charge elements.  Thick
+    elements need parts['sigma'] and parts['psigma']."""
     kind, par = _elements(elements)
     n = parts["x"].shape[0]
-    lib().orc_push(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
-                   _ptr(parts.get("lost")), len(kind), _ptr(kind), _ptr(par))
+    rc = lib().orc_push(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                        _ptr(parts["py"]), *_longitudinal(parts), _ptr(parts.get("lost")),
+                        len(kind), _ptr(kind), _ptr(par))
+    if rc != 0:
+        raise ValueError("thick elements need sigma and psigma, and n >= 1 sextupole steps")
 
 
 def deposit(parts: dict, grid) -> tuple[np.ndarray, int]:
@@ -206,6 +221,9 @@ def track(parts: dict, grid, elements, n_turns: int, solver: str = "open") -> No
     """In place: n_turns through the one-turn element sequence."""
     kind, par = _elements(elements)
     n = parts["x"].shape[0]
-    lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]), _ptr(parts["py"]),
-                    _ptr(parts.get("lost")), _ptr(_weights(parts)), *_grid_args(grid), len(kind),
-                    _ptr(kind), _ptr(par), int(n_turns), _pipe(solver))
+    rc = lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                         _ptr(parts["py"]), *_longitudinal(parts), _ptr(parts.get("lost")),
+                         _ptr(_weights(parts)), *_grid_args(grid), len(kind), _ptr(kind),
+                         _ptr(par), int(n_turns), _pipe(solver))
+    if rc != 0:
+        raise ValueError("thick elements need sigma and psigma, and n >= 1 sextupole steps")

@@ -15,7 +15,9 @@
  *
  * Conventions (shared by the tests):
  *   particles   structure of arrays x, px, y, py (m, rad); lost[p] != 0 means
- *               the particle has left the grid and is frozen.
+ *               the particle has left the grid and is frozen.  Lattices with
+ *               thick elements also carry sigma = s - c beta0 t (m) and its
+ *               conjugate p_sigma (Sec. III); other elements leave them alone.
  *   grid        nx, ny nodes at x_min + i*dx, y_min + j*dy; node arrays are
  *               row-major [i*ny + j] (i along x).
  *   elements    kind[e], par[e*16 + k]:
@@ -23,6 +25,10 @@
  *                 2 LIN4X4   par[0..15] row-major on (x, px, y, py)
  *                 3 SEXTUPOLE_THIN  par[0] = k2*L
  *                 4 SPACE_CHARGE    par[0] = kick coefficient kappa
+ *                 5 QUAD_THICK      par[0] = k1 (1/m^2), par[1] = L (m),
+ *                                   par[2] = 1/gamma0^2
+ *                 6 SEXT_THICK      par[0] = k2 (1/m^3), par[1] = L (m),
+ *                                   par[2] = 1/gamma0^2, par[3] = steps n >= 1
  */
 #include <math.h>
 #include <stdint.h>
@@ -36,6 +42,8 @@
 #define ORC_LIN4X4 2
 #define ORC_SEXT_THIN 3
 #define ORC_SC 4
+#define ORC_QUAD_THICK 5
+#define ORC_SEXT_THICK 6
 
 /* Fixed-point charge assignment: 12 fractional bits per axis, so the four
  * weights of one particle sum to exactly 2^24 charge units. */
@@ -80,37 +88,156 @@ int orc_num_threads(void)
  * the kick step of the split thick-sextupole integrator of Sec. III-C with the
  * drift parts removed: with V = k2 (x^3 - 3 x y^2) / 6 and integrated strength
  * k2*L, the momenta change by -dV/dx * L and -dV/dy * L. */
-static void push_one(double *x, double *px, double *y, double *py, int kind, const double *m)
+static void push_linear(double v[6], int kind, const double *m)
 {
-    double X = *x, PX = *px, Y = *y, PY = *py;
+    double X = v[0], PX = v[1], Y = v[2], PY = v[3];
     if (kind == ORC_LIN2X2) {
-        *x = m[0] * X + m[1] * PX;
-        *px = m[2] * X + m[3] * PX;
-        *y = m[4] * Y + m[5] * PY;
-        *py = m[6] * Y + m[7] * PY;
+        v[0] = m[0] * X + m[1] * PX;
+        v[1] = m[2] * X + m[3] * PX;
+        v[2] = m[4] * Y + m[5] * PY;
+        v[3] = m[6] * Y + m[7] * PY;
     } else if (kind == ORC_LIN4X4) {
-        *x = m[0] * X + m[1] * PX + m[2] * Y + m[3] * PY;
-        *px = m[4] * X + m[5] * PX + m[6] * Y + m[7] * PY;
-        *y = m[8] * X + m[9] * PX + m[10] * Y + m[11] * PY;
-        *py = m[12] * X + m[13] * PX + m[14] * Y + m[15] * PY;
+        v[0] = m[0] * X + m[1] * PX + m[2] * Y + m[3] * PY;
+        v[1] = m[4] * X + m[5] * PX + m[6] * Y + m[7] * PY;
+        v[2] = m[8] * X + m[9] * PX + m[10] * Y + m[11] * PY;
+        v[3] = m[12] * X + m[13] * PX + m[14] * Y + m[15] * PY;
     } else if (kind == ORC_SEXT_THIN) {
         double k2l = m[0];
-        *px = PX - 0.5 * k2l * (X * X - Y * Y);
-        *py = PY + k2l * X * Y;
+        v[1] = PX - 0.5 * k2l * (X * X - Y * Y);
+        v[3] = PY + k2l * X * Y;
     }
 }
 
-/* Apply the non-space-charge elements in order; lost particles are frozen. */
-void orc_push(int64_t n, double *x, double *px, double *y, double *py, const uint8_t *lost,
-              int n_el, const int32_t *kind, const double *par)
+/* One transverse plane of the thick quadrupole (Sec. III-B), the exact flow of
+ * H_approx (eq. H, h = 0, e A_s / p0 = -k1 (x^2 - y^2) / 2) over length L:
+ * with q = 1 - p_sigma the plane obeys u' = q p_u, p_u' = -K u, where K = k1
+ * for x and K = -k1 for y.  A focusing plane (K > 0) turns by the angle
+ * sqrt(K q) L:
+ *   u(L)   = u cos + sqrt(q/K) p_u sin,    p_u(L) = p_u cos - sqrt(K/q) u sin;
+ * a defocusing plane takes cosh and sinh, with the sign of the second p_u term
+ * flipped; K = 0 is the drift u(L) = u + q p_u L.  Returns the integral of
+ * p_u(s)^2 over the element, which the path-length equation needs: writing
+ * p_u(s) = A c(s) + B s(s) with the plane's pair of functions,
+ *   focusing    A^2 (L/2 + sin(2 phi)/(4 w)) + A B sin(phi)^2 / w
+ *               + B^2 (L/2 - sin(2 phi)/(4 w)),
+ *   defocusing  A^2 (L/2 + sinh(2 phi)/(4 w)) + A B sinh(phi)^2 / w
+ *               + B^2 (sinh(2 phi)/(4 w) - L/2),
+ * where w = sqrt(|K| q) and phi = w L. */
+static double quad_plane(double *u, double *pu, double K, double q, double L)
 {
+    double u0 = *u, p0 = *pu;
+    if (K == 0.0) {
+        *u = u0 + q * p0 * L;
+        return p0 * p0 * L;
+    }
+    double k = fabs(K);
+    double w = sqrt(k * q);
+    double phi = w * L;
+    double A = p0, B;
+    if (K > 0.0) {
+        double c = cos(phi), s = sin(phi);
+        *u = u0 * c + sqrt(q / k) * p0 * s;
+        *pu = p0 * c - sqrt(k / q) * u0 * s;
+        B = -sqrt(k / q) * u0;
+        double s2 = sin(2.0 * phi) / (4.0 * w);
+        return A * A * (0.5 * L + s2) + A * B * s * s / w + B * B * (0.5 * L - s2);
+    }
+    double c = cosh(phi), s = sinh(phi);
+    *u = u0 * c + sqrt(q / k) * p0 * s;
+    *pu = p0 * c + sqrt(k / q) * u0 * s;
+    B = sqrt(k / q) * u0;
+    double s2 = sinh(2.0 * phi) / (4.0 * w);
+    return A * A * (0.5 * L + s2) + A * B * s * s / w + B * B * (s2 - 0.5 * L);
+}
+
+/* Thick quadrupole with chromatic focusing (Sec. III-B): both planes as above
+ * with q = 1 - p_sigma; p_sigma is constant and
+ *   sigma(L) = sigma(0) + p_sigma L / gamma0^2 - (1/2) int_0^L (px^2 + py^2) ds. */
+static void push_quad_thick(double v[6], const double *m)
+{
+    double k1 = m[0], L = m[1], ig2 = m[2];
+    double q = 1.0 - v[5];
+    double ix = quad_plane(&v[0], &v[1], k1, q, L);
+    double iy = quad_plane(&v[2], &v[3], -k1, q, L);
+    v[4] = v[4] + v[5] * L * ig2 - 0.5 * (ix + iy);
+}
+
+/* Exact flow of H0 = (px^2 + py^2)/2 + p_sigma^2/(2 gamma0^2)
+ *                   - (px^2 + py^2) p_sigma / 2      (Sec. III-C)
+ * over length t: the momenta are constant, dx/ds = px (1 - p_sigma),
+ * dy/ds = py (1 - p_sigma), dsigma/ds = p_sigma/gamma0^2 - (px^2 + py^2)/2. */
+static void flow_h0(double v[6], double t, double ig2)
+{
+    double q = 1.0 - v[5];
+    v[0] = v[0] + v[1] * q * t;
+    v[2] = v[2] + v[3] * q * t;
+    v[4] = v[4] + (v[5] * ig2 - 0.5 * (v[1] * v[1] + v[3] * v[3])) * t;
+}
+
+/* Exact flow of V = k2 (x^3 - 3 x y^2) / 6 over length t: positions fixed,
+ * px -= dV/dx t = (k2/2)(x^2 - y^2) t,  py -= dV/dy t = -k2 x y t. */
+static void flow_v(double v[6], double t, double k2)
+{
+    double X = v[0], Y = v[2];
+    v[1] = v[1] - 0.5 * k2 * (X * X - Y * Y) * t;
+    v[3] = v[3] + k2 * X * Y * t;
+}
+
+/* Thick sextupole (Sec. III-C, eq. Sym2): H_approx = H0 + V is advanced by the
+ * symmetric product of exact flows
+ *   H0 over a h, V over b h, H0 over c h, V over b h, H0 over a h
+ * with a = (1 - 1/sqrt 3)/2, b = 1/2, c = 1/sqrt 3, applied n times with
+ * h = L / n (n = 1 is one product over the whole element). */
+static void push_sext_thick(double v[6], const double *m)
+{
+    double k2 = m[0], L = m[1], ig2 = m[2];
+    int n = (int)m[3];
+    double h = L / (double)n;
+    double c = 1.0 / sqrt(3.0);
+    double a = 0.5 * (1.0 - c), b = 0.5;
+    for (int i = 0; i < n; ++i) {
+        flow_h0(v, a * h, ig2);
+        flow_v(v, b * h, k2);
+        flow_h0(v, c * h, ig2);
+        flow_v(v, b * h, k2);
+        flow_h0(v, a * h, ig2);
+    }
+}
+
+static int is_thick(int kind) { return kind == ORC_QUAD_THICK || kind == ORC_SEXT_THICK; }
+
+/* Apply the non-space-charge elements in order; lost particles are frozen.
+ * sigma and psigma may be NULL when no element is thick; returns -1 (and
+ * moves nothing) when a thick element meets NULL longitudinal arrays or a
+ * thick sextupole has n < 1 steps. */
+int orc_push(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
+             double *psigma, const uint8_t *lost, int n_el, const int32_t *kind, const double *par)
+{
+    for (int e = 0; e < n_el; ++e) {
+        if (is_thick(kind[e]) && (!sigma || !psigma)) return -1;
+        if (kind[e] == ORC_SEXT_THICK && par[16 * e + 3] < 1.0) return -1;
+    }
     int64_t p;
 #pragma omp parallel for schedule(static)
     for (p = 0; p < n; ++p) {
         if (lost && lost[p]) continue;
-        for (int e = 0; e < n_el; ++e)
-            if (kind[e] != ORC_SC) push_one(&x[p], &px[p], &y[p], &py[p], kind[e], par + 16 * e);
+        double v[6] = {x[p], px[p], y[p], py[p], sigma ? sigma[p] : 0.0, psigma ? psigma[p] : 0.0};
+        for (int e = 0; e < n_el; ++e) {
+            const double *m = par + 16 * e;
+            if (kind[e] == ORC_QUAD_THICK)
+                push_quad_thick(v, m);
+            else if (kind[e] == ORC_SEXT_THICK)
+                push_sext_thick(v, m);
+            else if (kind[e] != ORC_SC)
+                push_linear(v, kind[e], m);
+        }
+        x[p] = v[0];
+        px[p] = v[1];
+        y[p] = v[2];
+        py[p] = v[3];
+        if (sigma) sigma[p] = v[4];
     }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -398,18 +525,25 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
 /* Track n_turns through the element sequence of one turn: non-space-charge
  * elements are pushed, each space-charge element runs the full step above with
  * its own kappa.  The charge scale is 1/(2^24 n): n is the initial particle
- * count, so lost particles take their charge with them. */
-void orc_track(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
-               const float *wt, int nx, int ny, double x_min, double y_min, double dx, double dy,
-               int n_el, const int32_t *kind, const double *par, int n_turns, int pipe)
+ * count, so lost particles take their charge with them.  Returns -1 (nothing
+ * tracked) under the conditions orc_push rejects. */
+int orc_track(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
+              double *psigma, uint8_t *lost, const float *wt, int nx, int ny, double x_min,
+              double y_min, double dx, double dy, int n_el, const int32_t *kind,
+              const double *par, int n_turns, int pipe)
 {
     double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
+    for (int e = 0; e < n_el; ++e) {
+        if (is_thick(kind[e]) && (!sigma || !psigma)) return -1;
+        if (kind[e] == ORC_SEXT_THICK && par[16 * e + 3] < 1.0) return -1;
+    }
     for (int t = 0; t < n_turns; ++t)
         for (int e = 0; e < n_el; ++e) {
             if (kind[e] == ORC_SC)
                 orc_space_charge(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale,
                                  par[16 * e], NULL, NULL, pipe);
             else
-                orc_push(n, x, px, y, py, lost, 1, kind + e, par + 16 * e);
+                orc_push(n, x, px, y, py, sigma, psigma, lost, 1, kind + e, par + 16 * e);
         }
+    return 0;
 }

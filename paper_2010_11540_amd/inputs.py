@@ -25,7 +25,7 @@ import math
 import numpy as np
 
 # element kinds (same numbering as the C ABI's scpic_element_kind)
-LIN2X2, LIN4X4, SEXT_THIN, SC = 1, 2, 3, 4
+LIN2X2, LIN4X4, SEXT_THIN, SC, QUAD_THICK, SEXT_THICK = 1, 2, 3, 4, 5, 6
 
 ELEMENT_DTYPE = np.dtype([("kind", "<i4"), ("pad", "<i4"), ("p", "<f8", (16,))], align=True)
 assert ELEMENT_DTYPE.itemsize == 136
@@ -66,6 +66,25 @@ def gaussian_beam(n: int, seed: int, sigma_x=1e-3, sigma_px=1e-3, sigma_y=1e-3, 
         "px": np.ascontiguousarray(z[1] * sigma_px),
         "y": np.ascontiguousarray(z[2] * sigma_y),
         "py": np.ascontiguousarray(z[3] * sigma_py),
+    }
+    if lost:
+        parts["lost"] = np.zeros(n, dtype=np.uint8)
+    return parts
+
+
+def gaussian_beam6d(n: int, seed: int, sigma_x=1e-3, sigma_px=1e-3, sigma_y=1e-3, sigma_py=1e-3,
+                    sigma_z=1.0, sigma_ps=1e-3, lost: bool = True) -> dict:
+    """Gaussian in all six canonical coordinates (x, px, y, py, sigma, p_sigma),
+    uncorrelated: the transverse part of a long bunch with a momentum spread."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((6, n))
+    parts = {
+        "x": np.ascontiguousarray(z[0] * sigma_x),
+        "px": np.ascontiguousarray(z[1] * sigma_px),
+        "y": np.ascontiguousarray(z[2] * sigma_y),
+        "py": np.ascontiguousarray(z[3] * sigma_py),
+        "sigma": np.ascontiguousarray(z[4] * sigma_z),
+        "psigma": np.ascontiguousarray(z[5] * sigma_ps),
     }
     if lost:
         parts["lost"] = np.zeros(n, dtype=np.uint8)
@@ -161,6 +180,27 @@ def sext_thin(k2l: float) -> np.ndarray:
     return e
 
 
+def quad_thick(k1: float, length: float, inv_gamma2: float) -> np.ndarray:
+    """Thick quadrupole with chromatic focusing (Sec. III-B); k1 > 0 focuses x."""
+    e = elements(1)
+    e["kind"] = QUAD_THICK
+    e["p"][0, :3] = (k1, length, inv_gamma2)
+    return e
+
+
+def sext_thick(k2: float, length: float, inv_gamma2: float, steps: int = 1) -> np.ndarray:
+    """Thick sextupole by the symmetric split of Sec. III-C, applied `steps`
+    times over length/steps; k2 = 0 is the exact drift of H0."""
+    e = elements(1)
+    e["kind"] = SEXT_THICK
+    e["p"][0, :4] = (k2, length, inv_gamma2, float(steps))
+    return e
+
+
+def drift(length: float, inv_gamma2: float) -> np.ndarray:
+    return sext_thick(0.0, length, inv_gamma2, 1)
+
+
 def sc_kick(kappa: float) -> np.ndarray:
     e = elements(1)
     e["kind"] = SC
@@ -218,6 +258,40 @@ def ring(qx: float, qy: float, n_seg: int, kappa: float, beta: float = 1.0,
     return np.concatenate(parts)
 
 
+# 3 GeV kinetic energy protons (the Main Ring's injection energy)
+GAMMA0_3GEV = 1.0 + 3.0 / PROTON_MASS_GEV
+
+
+def fodo_thick(n_cell: int, q: float, kappa: float | None, cell_length: float = 4.0,
+               quad_length: float = 0.5, sext_length: float = 0.2, k2f: float = 20.0,
+               k2d: float = -30.0, gamma0: float = GAMMA0_3GEV, sext_steps: int = 1) -> np.ndarray:
+    """One turn of n_cell thick FODO cells, each
+         [QF/2, D, SF, D, QD, D, SD, D, QF/2, SC kick]
+    (the kick sits at the middle of QF, where alpha = 0).  The quadrupole
+    gradient is set from the thin-lens FODO relation for a phase advance of
+    2 pi q / n_cell per cell, f = L_cell / (4 sin(mu/2)), k1 = 1 / (f L_quad);
+    the thick magnets make the actual advance slightly different."""
+    ig2 = 1.0 / (gamma0 * gamma0)
+    mu = 2.0 * math.pi * q / n_cell
+    k1 = 4.0 * math.sin(0.5 * mu) / (cell_length * quad_length)
+    d = 0.25 * (cell_length - 2.0 * quad_length - 2.0 * sext_length)
+    cell = [quad_thick(k1, 0.5 * quad_length, ig2), drift(d, ig2),
+            sext_thick(k2f, sext_length, ig2, sext_steps), drift(d, ig2),
+            quad_thick(-k1, quad_length, ig2), drift(d, ig2),
+            sext_thick(k2d, sext_length, ig2, sext_steps), drift(d, ig2),
+            quad_thick(k1, 0.5 * quad_length, ig2)]
+    if kappa is not None:
+        cell.append(sc_kick(kappa))
+    return np.concatenate(cell * n_cell)
+
+
+def fodo_beta(n_cell: int, q: float, cell_length: float = 4.0) -> tuple[float, float]:
+    """Thin-lens FODO beta at the focusing and defocusing quadrupole centres."""
+    mu = 2.0 * math.pi * q / n_cell
+    s = math.sin(0.5 * mu)
+    return (cell_length * (1 + s) / math.sin(mu), cell_length * (1 - s) / math.sin(mu))
+
+
 # --------------------------------------------------------------------------
 # the five workloads
 # --------------------------------------------------------------------------
@@ -261,6 +335,21 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
         lat = ring(4.2, 4.3, 200, kc / 200)
         return {"name": name, "parts": long_bunch_kv(n, seed, a, b), "grid": grid, "lattice": lat,
                 "turns": 1000, "n": n, "seed": seed}
+    elif name in ("thick", "thick_small"):
+        # 6D beam through thick chromatic quadrupoles and SABA2 thick
+        # sextupoles: 1 mm rms at the kick in both planes, p_sigma rms 1e-3
+        big = name == "thick"
+        n = (1_000_000 if big else 10_000) if n is None else n
+        seed = SEED_BASE + (6 if big else 7) if seed is None else seed
+        grid = make_grid(128 if big else 64)
+        n_cell = 100 if big else 16
+        bx, by = fodo_beta(n_cell, 4.2)
+        eps_x = 1e-6 / bx
+        lat = fodo_thick(n_cell, 4.2, kappa_for_tune_shift(-0.2, eps_x, n_cell))
+        parts = gaussian_beam6d(n, seed, 1e-3, 1e-3 / bx, 1e-3 * math.sqrt(by / bx),
+                                1e-3 / math.sqrt(bx * by))
+        return {"name": name, "parts": parts, "grid": grid, "lattice": lat,
+                "turns": 10 if big else 10, "n": n, "seed": seed}
     else:
         raise ValueError(f"unknown workload {name!r}")
     return {"name": name, "parts": gaussian_beam(n, seed), "grid": grid, "lattice": lat,
