@@ -32,6 +32,7 @@ sys.path.insert(0, str(ROOT))
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64  # read + write x, px, y, py in FP64
 BYTES_PER_WEIGHT = 4          # + the FP32 line-density kick weight (2.5D long bunch)
+BYTES_PER_LONGITUDINAL = 24   # + read sigma, p_sigma and write sigma (thick elements, 6D)
 PROFILE_TRAFFIC = ROOT / "profiles" / "pass_traffic_production.json"
 PASS_SOURCE = ROOT / "paper_2010_11540_amd" / "csrc" / "particles.hip"
 
@@ -46,7 +47,7 @@ def parse():
                     help="untimed SC steps before timing (default: 200 for production, 2 turns "
                          "otherwise)")
     ap.add_argument("--workload", default="production",
-                    choices=["production", "small", "large", "batch"],
+                    choices=["production", "small", "large", "batch", "thick"],
                     help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
                          "bunch with line-density kick weights, 256^2; batch: 64-beam tune scan")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -132,6 +133,9 @@ WORKLOAD_TEXT = {
     "small": "small 2D PIC: 1e4 Gaussian particles, 64x64 grid, 16 SC steps/turn",
     "large": ("large 2.5D PIC: 1e7 KV 2:1 long-bunch particles with 128-bin line-density kick "
               "weights, 256x256 grid, 200 SC steps/turn"),
+    "thick": ("6D thick-element PIC: 1e6 Gaussian particles (x, px, y, py, sigma, p_sigma), "
+              "128x128 grid, per turn 100 FODO cells of 3 chromatic thick quadrupoles + 2 SABA2 "
+              "thick sextupoles + 4 drifts, 100 SC steps"),
     "batch": ("tune scan: 64 independent Gaussian beams of 1e4..5e5 particles (8.1e6 in all) on "
               "64x64 / 128x128 grids, tunes on an 8x8 lattice in [4.05, 4.45]^2, 16 SC steps/turn"),
 }
@@ -252,6 +256,7 @@ def main():
               "the space-charge loop is not sharded across GPUs in this build.", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_2010_11540_amd import inputs, scpic
@@ -309,10 +314,11 @@ def main():
     value = n * args.steps / seconds
     alive = int((d["lost"] == 0).sum().item())
 
-    # dominant kernel: the fused pass (kick + 4x4 map + deposit), timed alone
-    # on the same stream over a copy of the beam
+    # dominant kernel: the fused pass (kick + the elements of the turn's first
+    # segment + deposit), timed alone on the same stream over a copy of the beam
     d2 = {k: v.clone() for k, v in d.items()}
-    one_map = lat[lat["kind"] != inputs.SC][:1]
+    first_sc = int(np.nonzero(lat["kind"] == inputs.SC)[0][0])
+    one_map = lat[:first_sc]
     kappa = float(lat["p"][lat["kind"] == inputs.SC][0, 0])
     scale = 1.0 / ((1 << 24) * n)
     for _ in range(5):
@@ -335,18 +341,20 @@ def main():
     g1.record(stream)
     torch.cuda.synchronize()
     grid_us = g0.elapsed_time(g1) * 1e3 / args.pass_reps
-    unit_bytes = BYTES_PER_PARTICLE_STEP + (BYTES_PER_WEIGHT if "w" in d else 0)
+    six = "sigma" in d and bool(np.isin(one_map["kind"], (inputs.QUAD_THICK, inputs.SEXT_THICK)).any())
+    unit_bytes = (BYTES_PER_PARTICLE_STEP + (BYTES_PER_WEIGHT if "w" in d else 0)
+                  + (BYTES_PER_LONGITUDINAL if six else 0))
     achieved = unit_bytes * n / (pass_us * 1e-6) / 1e9
+    seg = {"production": "4x4 map", "thick": "FODO cell of thick elements"}.get(args.workload, "2x2 map")
     roofline = {
         "bound": "hbm",
-        "kernel": (f"k_pass<{'double' if args.precision == 'fp64' else 'float'},kick,deposit> "
-                   f"(gather+kick, {'4x4' if args.workload == 'production' else '2x2'} map, "
-                   "CIC deposit, flush)"),
+        "kernel": (f"k_pass<{'double' if args.precision == 'fp64' else 'float'},kick,deposit"
+                   f"{',six' if six else ''}> (gather+kick, {seg}, CIC deposit, flush)"),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(n),
+        "traffic": measured_traffic(n) if args.workload == "production" else None,
         "algorithmic_bytes_per_launch": unit_bytes * n,
         "avg_launch_us": round(pass_us, 3),
         "grid_phase_us": round(grid_us, 3),

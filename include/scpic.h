@@ -77,12 +77,17 @@ typedef struct {
  * lost (device, n bytes, may be NULL): nonzero marks a particle that has left
  * the grid domain at a deposit or kick; a lost particle is frozen (no push,
  * kick or deposit) and keeps its last coordinates.  With lost == NULL,
- * particles outside the domain simply take no part in deposit and kick. */
+ * particles outside the domain simply take no part in deposit and kick.
+ * sigma, psigma (device, n doubles each, may both be NULL): the longitudinal
+ * canonical pair of Sec. III, sigma = s - c beta0 t (m) and p_sigma.  Required
+ * (SCPIC_EINVAL otherwise) when a lattice holds thick elements, which advance
+ * sigma and read p_sigma; every other element leaves both alone. */
 typedef struct {
     double *x, *px, *y, *py;
     const float *w;
     uint8_t *lost;
     int64_t n;
+    double *sigma, *psigma;
 } scpic_particles;
 
 /* ---- lattice elements (Sec. III) --------------------------------------- */
@@ -95,6 +100,23 @@ typedef struct {
  *                       px -= (k2L/2)(x^2 - y^2),  py += k2L x y
  *   SCPIC_EL_SC         p[0] = kappa: a space-charge location (deposit,
  *                       solve and kick with coefficient kappa)
+ *   SCPIC_EL_QUAD_THICK p[0] = k1 (1/m^2, > 0 focuses x), p[1] = L (m),
+ *                       p[2] = 1/gamma0^2: the thick quadrupole with
+ *                       chromatic focusing of Sec. III-B, the exact flow of
+ *                       H_approx (eq. H) over L; with q = 1 - p_sigma each
+ *                       plane turns by sqrt(|k1| q) L (cos/sin in the
+ *                       focusing plane, cosh/sinh in the other) and
+ *                       sigma += p_sigma L/gamma0^2 - (1/2) int (px^2+py^2) ds
+ *   SCPIC_EL_SEXT_THICK p[0] = k2 (1/m^3), p[1] = L (m), p[2] = 1/gamma0^2,
+ *                       p[3] = n (an integer in [1, 1024]): the thick
+ *                       sextupole of Sec. III-C, n times the symmetric product
+ *                       of exact flows H0 (a h), V (h/2), H0 (c h), V (h/2),
+ *                       H0 (a h) with h = L/n, c = 1/sqrt 3, a = (1 - c)/2,
+ *                       H0 = (px^2 + py^2)(1 - p_sigma)/2 + p_sigma^2/(2 gamma0^2),
+ *                       V = k2 (x^3 - 3 x y^2)/6; k2 = 0 is the exact drift
+ * The thick elements need the particles' sigma and psigma and are evaluated in
+ * FP64 with the device's sin, cos, expm1 and sqrt (results agree with any
+ * other correctly implemented evaluation to rounding, not bit for bit).
  * Linear maps are evaluated as written in row order, left to right, with no
  * fused multiply-add, so a push is bit-identical to the same sums in IEEE
  * FP64.  sizeof(scpic_element) == 136. */
@@ -102,6 +124,8 @@ typedef struct {
 #define SCPIC_EL_LIN4X4 2
 #define SCPIC_EL_SEXT_THIN 3
 #define SCPIC_EL_SC 4
+#define SCPIC_EL_QUAD_THICK 5
+#define SCPIC_EL_SEXT_THICK 6
 typedef struct {
     int32_t kind;
     int32_t reserved;

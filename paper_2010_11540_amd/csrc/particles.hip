@@ -8,6 +8,7 @@
 // sums evaluated anywhere else.
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "scpic_internal.h"
 
@@ -92,6 +93,88 @@ __device__ __forceinline__ void apply_element(int kind, const double *__restrict
         const double k2l = m[0];
         px = PX - 0.5 * k2l * (X * X - Y * Y);
         py = PY + k2l * X * Y;
+    }
+}
+
+// One transverse plane of the thick quadrupole (Sec. III-B) over length L:
+// u' = q p_u and p_u' = -K u with q = 1 - p_sigma, K = k1 for x and -k1 for y.
+// With w = sqrt|K q|, C = cos(w L) or cosh(w L) and S = sin(w L)/w or
+// sinh(w L)/w (S = L when K = 0), the flow is u <- u C + q p_u S,
+// p_u <- p_u C - K u S.  Returns the integral of p_u^2 over the element, taken
+// from the plane's invariant E = q p_u^2 + K u^2: d(u p_u)/ds = 2 q p_u^2 - E,
+// so the integral is (E L + u(L) p_u(L) - u(0) p_u(0)) / (2 q).
+// cosh and sinh come from one expm1, which keeps sinh accurate at small w L.
+__device__ __forceinline__ double quad_plane(double &u, double &pu, double K, double q, double L)
+{
+    const double u0 = u, p0 = pu;
+    const double kq = K * q;
+    double c, sw;
+    if (kq > 0.0) {
+        const double w = sqrt(kq);
+        double sn;
+        sincos(w * L, &sn, &c);
+        sw = sn / w;
+    } else if (kq < 0.0) {
+        const double w = sqrt(-kq);
+        const double em = expm1(w * L);
+        const double e = em + 1.0;
+        c = 0.5 * (e + 1.0 / e);
+        sw = 0.5 * (em + em / e) / w;
+    } else {
+        c = 1.0;
+        sw = L;
+    }
+    u = u0 * c + q * p0 * sw;
+    pu = p0 * c - K * u0 * sw;
+    const double inv = q * p0 * p0 + K * u0 * u0;
+    return (inv * L + u * pu - u0 * p0) / (2.0 * q);
+}
+
+// One element applied to one particle in six dimensions (Sec. III): the
+// four-dimensional elements as above (sigma, p_sigma untouched), the thick
+// quadrupole with chromatic focusing (Sec. III-B), whose path length is
+//   sigma += p_sigma L / gamma0^2 - (1/2) int (px^2 + py^2) ds,
+// and the thick sextupole (Sec. III-C) as n symmetric products of the exact
+// flows of H0 = (px^2 + py^2)(1 - p_sigma)/2 + p_sigma^2/(2 gamma0^2) and of
+// V = k2 (x^3 - 3 x y^2)/6 over the step h = L/n:
+//   H0 (a h), V (h/2), H0 (c h), V (h/2), H0 (a h),  c = 1/sqrt 3, a = (1 - c)/2.
+// p_sigma is constant in every element.
+__device__ __forceinline__ void apply_element6(int kind, const double *__restrict__ m, double &x,
+                                               double &px, double &y, double &py, double &sg,
+                                               double psg)
+{
+    if (kind == SCPIC_EL_QUAD_THICK) {
+        const double k1 = m[0], L = m[1], ig2 = m[2];
+        const double q = 1.0 - psg;
+        const double ix = quad_plane(x, px, k1, q, L);
+        const double iy = quad_plane(y, py, -k1, q, L);
+        sg = sg + (psg * ig2 * L - 0.5 * (ix + iy));
+    } else if (kind == SCPIC_EL_SEXT_THICK) {
+        constexpr double kC = 0.57735026918962576451;  // 1/sqrt(3)
+        constexpr double kA = 0.5 * (1.0 - kC);
+        const int n = (int)m[3];
+        const double h = m[1] / (double)n;
+        const double q = 1.0 - psg, dsg = psg * m[2];
+        const double ta = kA * h, tc = kC * h, tv = 0.5 * h * m[0];
+        auto drift = [&](double t) {
+            x = x + px * q * t;
+            y = y + py * q * t;
+            sg = sg + (dsg - 0.5 * (px * px + py * py)) * t;
+        };
+        auto kick = [&]() {
+            const double X = x, Y = y;
+            px = px - 0.5 * tv * (X * X - Y * Y);
+            py = py + tv * X * Y;
+        };
+        for (int i = 0; i < n; ++i) {
+            drift(ta);
+            kick();
+            drift(tc);
+            kick();
+            drift(ta);
+        }
+    } else {
+        apply_element(kind, m, x, px, y, py);
     }
 }
 
@@ -219,10 +302,12 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // node the kick gathers from, is staged in LDS beside the tile when it fits.
 // At the end each workgroup writes the bounding box of its tile cells to its
 // slice of the partials (no global atomics).
+// SIX: the particles carry sigma and p_sigma and els may hold thick
+// elements; sigma is loaded and stored with the transverse coordinates.
 // The body is shared by the single-beam kernel and the batched one: bid is
 // the workgroup's index among the nblk workgroups working on beam P (its
 // slice of the partials and its header), T = nblk * blockDim.x.
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom &g,
                                           const TE *__restrict__ ef, double kappa,
                                           const PassElements &els, const DepositTarget &dep,
@@ -236,7 +321,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     int64_t p = (int64_t)bid * blockDim.x + threadIdx.x;
 
     // first particle's loads go out before the LDS set-up
-    double x = 0, px = 0, y = 0, py = 0;
+    double x = 0, px = 0, y = 0, py = 0, sg = 0, psg = 0;
     float wp = 1.0f;
     uint8_t lf = 1;
     if (p < P.n) {
@@ -244,6 +329,10 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         px = P.px[p];
         y = P.y[p];
         py = P.py[p];
+        if constexpr (SIX) {
+            sg = P.sigma[p];
+            psg = P.psigma[p];
+        }
         lf = P.lost ? P.lost[p] : 0;
         if (KICK && P.w) wp = P.w[p];
     }
@@ -318,7 +407,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     int bi0 = INT_MAX, bi1 = -1, bj0 = INT_MAX, bj1 = -1, cnt = 0;
     for (; p < P.n; p += T) {
         const int64_t pn = p + T;
-        double xn = 0, pxn = 0, yn = 0, pyn = 0;
+        double xn = 0, pxn = 0, yn = 0, pyn = 0, sgn = 0, psgn = 0;
         float wn = 1.0f;
         uint8_t lfn = 1;
         if (pn < P.n) {
@@ -326,6 +415,10 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             pxn = P.px[pn];
             yn = P.y[pn];
             pyn = P.py[pn];
+            if constexpr (SIX) {
+                sgn = P.sigma[pn];
+                psgn = P.psigma[pn];
+            }
             lfn = P.lost ? P.lost[pn] : 0;
             if (KICK && P.w) wn = P.w[pn];
         }
@@ -347,12 +440,19 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             }
         }
         if (act) {
-            for (int e = 0; e < els.n_el; ++e) apply_element(els.kind[e], els.p[e], x, px, y, py);
+            if constexpr (SIX) {
+                for (int e = 0; e < els.n_el; ++e)
+                    apply_element6(els.kind[e], els.p[e], x, px, y, py, sg, psg);
+            } else {
+                for (int e = 0; e < els.n_el; ++e)
+                    apply_element(els.kind[e], els.p[e], x, px, y, py);
+            }
             if (moves) {
                 P.x[p] = x;
                 P.px[p] = px;
                 P.y[p] = y;
                 P.py[p] = py;
+                if constexpr (SIX) P.sigma[p] = sg;
             }
             if constexpr (DEPOSIT) {
                 Cic c;
@@ -393,6 +493,10 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         px = pxn;
         y = yn;
         py = pyn;
+        if constexpr (SIX) {
+            sg = sgn;
+            psg = psgn;
+        }
         wp = wn;
         lf = lfn;
     }
@@ -440,19 +544,19 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     }
 }
 
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 __global__ void __launch_bounds__(1024)
     k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
            PassElements els, DepositTarget dep, unsigned lds_bytes)
 {
-    pass_body<TE, KICK, DEPOSIT>(P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x,
-                                 (int)gridDim.x);
+    pass_body<TE, KICK, DEPOSIT, SIX>(P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x,
+                                      (int)gridDim.x);
 }
 
 // One pass over every beam of a batch: workgroup -> beam from the batch's
 // table, then the same body on that beam's particles, grid, field and
 // partials with its own kick strength and elements (steps[beam]).
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 __global__ void __launch_bounds__(1024)
     k_pass_batched(BatchLaunch b, ParticlePtrs all, const BatchStep *__restrict__ steps,
                    unsigned lds_bytes)
@@ -464,11 +568,14 @@ __global__ void __launch_bounds__(1024)
     P.px = all.px + I.p0;
     P.y = all.y + I.p0;
     P.py = all.py + I.p0;
+    P.sigma = all.sigma ? all.sigma + I.p0 : nullptr;
+    P.psigma = all.psigma ? all.psigma + I.p0 : nullptr;
     P.w = all.w ? all.w + I.p0 : nullptr;
     P.lost = all.lost ? all.lost + I.p0 : nullptr;
     P.n = I.n;
-    pass_body<TE, KICK, DEPOSIT>(P, I.g, (const TE *)I.ef, steps[k].kappa, steps[k].els, I.dep,
-                                 lds_bytes, (int)blockIdx.x - I.pass_block0, I.pass_blocks);
+    pass_body<TE, KICK, DEPOSIT, SIX>(P, I.g, (const TE *)I.ef, steps[k].kappa, steps[k].els,
+                                      I.dep, lds_bytes, (int)blockIdx.x - I.pass_block0,
+                                      I.pass_blocks);
 }
 
 // Between two node arrays (ex, ey) and the internal interleaved layout ef
@@ -491,28 +598,46 @@ __global__ void __launch_bounds__(256)
 
 size_t g_lds_limit = 0;  // set by prepare_pass_kernels
 
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, const void *ef,
                          double kappa, const PassElements &els, const DepositTarget &dep,
                          int blocks, int threads)
 {
     const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
-    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), lds, s, p, g,
-                       (const TE *)ef, kappa, els, dep, (unsigned)lds);
+    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds, s, p,
+                       g, (const TE *)ef, kappa, els, dep, (unsigned)lds);
     return hipGetLastError();
 }
 
-template <typename TE, bool KICK, bool DEPOSIT>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                  const BatchStep *steps, int blocks, int threads)
 {
     const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
-    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), lds, s, b,
-                       all, steps, (unsigned)lds);
+    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds,
+                       s, b, all, steps, (unsigned)lds);
     return hipGetLastError();
 }
 
+template <typename TE, bool SIX>
+void pass_kernels_of(std::vector<const void *> &out)
+{
+    out.push_back((const void *)k_pass<TE, true, true, SIX>);
+    out.push_back((const void *)k_pass<TE, false, true, SIX>);
+    out.push_back((const void *)k_pass<TE, true, false, SIX>);
+    out.push_back((const void *)k_pass_batched<TE, true, true, SIX>);
+    out.push_back((const void *)k_pass_batched<TE, false, true, SIX>);
+    out.push_back((const void *)k_pass_batched<TE, true, false, SIX>);
+}
+
 }  // namespace
+
+bool has_thick(const PassElements &els)
+{
+    for (int e = 0; e < els.n_el; ++e)
+        if (els.kind[e] == SCPIC_EL_QUAD_THICK || els.kind[e] == SCPIC_EL_SEXT_THICK) return true;
+    return false;
+}
 
 // Allow the passes the dynamic LDS they use (beyond the default limit):
 // lds_limit is the device's per-workgroup LDS minus the kernel's static LDS.
@@ -520,18 +645,11 @@ hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const Part
 hipError_t prepare_pass_kernels(size_t lds_limit)
 {
     g_lds_limit = lds_limit;
-    const void *kerns[] = {(const void *)k_pass<double, true, true>,
-                           (const void *)k_pass<double, false, true>,
-                           (const void *)k_pass<double, true, false>,
-                           (const void *)k_pass<float, true, true>,
-                           (const void *)k_pass<float, false, true>,
-                           (const void *)k_pass<float, true, false>,
-                           (const void *)k_pass_batched<double, true, true>,
-                           (const void *)k_pass_batched<double, false, true>,
-                           (const void *)k_pass_batched<double, true, false>,
-                           (const void *)k_pass_batched<float, true, true>,
-                           (const void *)k_pass_batched<float, false, true>,
-                           (const void *)k_pass_batched<float, true, false>};
+    std::vector<const void *> kerns;
+    pass_kernels_of<double, false>(kerns);
+    pass_kernels_of<float, false>(kerns);
+    pass_kernels_of<double, true>(kerns);
+    pass_kernels_of<float, true>(kerns);
     for (const void *k : kerns) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_limit);
@@ -540,39 +658,44 @@ hipError_t prepare_pass_kernels(size_t lds_limit)
     return hipSuccess;
 }
 
+// The runtime flags as template arguments: L(TE, KICK, DEPOSIT, SIX) expands
+// to the launch of the matching instantiation.
+#define SCPIC_DISPATCH(L)                                                                     \
+    if (mixed) {                                                                              \
+        if (six)                                                                              \
+            return kick ? (deposit ? L(float, true, true, true) : L(float, true, false, true)) \
+                        : (deposit ? L(float, false, true, true)                              \
+                                   : L(float, false, false, true));                           \
+        return kick ? (deposit ? L(float, true, true, false) : L(float, true, false, false))  \
+                    : (deposit ? L(float, false, true, false) : L(float, false, false, false)); \
+    }                                                                                         \
+    if (six)                                                                                  \
+        return kick ? (deposit ? L(double, true, true, true) : L(double, true, false, true))  \
+                    : (deposit ? L(double, false, true, true) : L(double, false, false, true)); \
+    return kick ? (deposit ? L(double, true, true, false) : L(double, true, false, false))    \
+                : (deposit ? L(double, false, true, false) : L(double, false, false, false))
+
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
                        bool deposit, const DepositTarget &dep, int blocks, int threads)
 {
     if (blocks <= 0) return hipSuccess;
-    if (mixed) {
-        if (kick)
-            return deposit ? launch_pass_t<float, true, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
-                           : launch_pass_t<float, true, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
-        return deposit ? launch_pass_t<float, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
-                       : launch_pass_t<float, false, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
-    }
-    if (kick)
-        return deposit ? launch_pass_t<double, true, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
-                       : launch_pass_t<double, true, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
-    return deposit ? launch_pass_t<double, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
-                   : launch_pass_t<double, false, false>(s, p, g, ef, kappa, els, dep, blocks, threads);
+    const bool six = has_thick(els);
+#define SCPIC_L(T, K, D, S) launch_pass_t<T, K, D, S>(s, p, g, ef, kappa, els, dep, blocks, threads)
+    SCPIC_DISPATCH(SCPIC_L);
+#undef SCPIC_L
 }
 
 hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                const BatchStep *steps, bool kick, bool mixed, bool deposit,
-                               int blocks, int threads)
+                               bool six, int blocks, int threads)
 {
     if (blocks <= 0) return hipSuccess;
-#define SCPIC_PB(T, K, D) launch_pass_batched_t<T, K, D>(s, b, all, steps, blocks, threads)
-    if (mixed) {
-        if (kick) return deposit ? SCPIC_PB(float, true, true) : SCPIC_PB(float, true, false);
-        return deposit ? SCPIC_PB(float, false, true) : SCPIC_PB(float, false, false);
-    }
-    if (kick) return deposit ? SCPIC_PB(double, true, true) : SCPIC_PB(double, true, false);
-    return deposit ? SCPIC_PB(double, false, true) : SCPIC_PB(double, false, false);
-#undef SCPIC_PB
+#define SCPIC_L(T, K, D, S) launch_pass_batched_t<T, K, D, S>(s, b, all, steps, blocks, threads)
+    SCPIC_DISPATCH(SCPIC_L);
+#undef SCPIC_L
 }
+#undef SCPIC_DISPATCH
 
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
                              void *ef, int ncell)

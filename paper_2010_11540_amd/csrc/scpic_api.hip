@@ -145,6 +145,8 @@ ParticlePtrs to_ptrs(const scpic_particles *p)
     r.px = p->px;
     r.y = p->y;
     r.py = p->py;
+    r.sigma = p->sigma;
+    r.psigma = p->psigma;
     r.w = p->w;
     r.lost = p->lost;
     r.n = p->n;
@@ -168,13 +170,34 @@ scpic_status collect_elements(const scpic_element *els, int32_t n_el,
     if (n_el > 0 && !els) return fail(SCPIC_EINVAL, "elements pointer is NULL");
     for (int i = 0; i < n_el; ++i) {
         const int k = els[i].kind;
+        const double *m = els[i].p;
         if (k != SCPIC_EL_LIN2X2 && k != SCPIC_EL_LIN4X4 && k != SCPIC_EL_SEXT_THIN &&
-            k != SCPIC_EL_SC)
+            k != SCPIC_EL_SC && k != SCPIC_EL_QUAD_THICK && k != SCPIC_EL_SEXT_THICK)
             return fail(SCPIC_EINVAL, "element " + std::to_string(i) + " has unknown kind " +
                                           std::to_string(k));
+        if ((k == SCPIC_EL_QUAD_THICK || k == SCPIC_EL_SEXT_THICK) &&
+            !(std::isfinite(m[0]) && std::isfinite(m[1]) && std::isfinite(m[2])))
+            return fail(SCPIC_EINVAL, "element " + std::to_string(i) +
+                                          ": thick element parameters must be finite");
+        if (k == SCPIC_EL_SEXT_THICK &&
+            !(m[3] >= 1.0 && m[3] <= (double)kMaxSextSteps && m[3] == std::floor(m[3])))
+            return fail(SCPIC_EINVAL, "element " + std::to_string(i) +
+                                          ": thick sextupole steps must be an integer in [1, " +
+                                          std::to_string(kMaxSextSteps) + "]");
         if (k == SCPIC_EL_SC && !allow_sc) continue;
         out.push_back(&els[i]);
     }
+    return SCPIC_OK;
+}
+
+// Thick elements advance sigma with p_sigma: the particles must carry both.
+scpic_status check_longitudinal(const std::vector<const scpic_element *> &els,
+                                const scpic_particles *p)
+{
+    if (p->n == 0 || (p->sigma && p->psigma)) return SCPIC_OK;
+    for (const scpic_element *e : els)
+        if (e->kind == SCPIC_EL_QUAD_THICK || e->kind == SCPIC_EL_SEXT_THICK)
+            return fail(SCPIC_EINVAL, "thick elements need the particles' sigma and psigma");
     return SCPIC_OK;
 }
 
@@ -519,7 +542,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
 
 extern "C" {
 
-int32_t scpic_version(void) { return 100; }
+int32_t scpic_version(void) { return 200; }
 
 const char *scpic_last_error(void) { return g_last_error.c_str(); }
 
@@ -607,6 +630,7 @@ scpic_status scpic_push(scpic_ctx *ctx, const scpic_particles *parts,
     if (scpic_status st = check_parts(parts)) return st;
     std::vector<const scpic_element *> els;
     if (scpic_status st = collect_elements(elements, n_el, els, false)) return st;
+    if (scpic_status st = check_longitudinal(els, parts)) return st;
     if (els.empty() || parts->n == 0) return SCPIC_OK;
     std::vector<PassOp> ops;
     emit_segment(ops, false, 0.0, els, false);
@@ -672,6 +696,7 @@ scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t ki
     if (scpic_status st = collect_elements(elements, n_el, els, true)) return st;
     for (auto *e : els)
         if (e->kind == SCPIC_EL_SC) return fail(SCPIC_EINVAL, "a pass takes no SC element");
+    if (scpic_status st = check_longitudinal(els, parts)) return st;
     PassOp op;
     op.kick = kick != 0;
     op.kappa = kappa;
@@ -707,6 +732,7 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
     if (n_turns < 0) return fail(SCPIC_EINVAL, "n_turns is negative");
     std::vector<const scpic_element *> all;
     if (scpic_status st = collect_elements(turn, n_el, all, true)) return st;
+    if (scpic_status st = check_longitudinal(all, parts)) return st;
     if (n_turns == 0 || all.empty() || parts->n == 0) return SCPIC_OK;
     const double scale = 1.0 / (kChargeOne * (double)parts->n);
 
@@ -753,6 +779,7 @@ namespace {
 struct BatchSchedule {
     std::vector<unsigned char> key;
     std::vector<PassOp> shape;     // kick / deposit per op (kappa, els unused)
+    std::vector<char> six;         // per op: some beam's elements are thick
     BatchStep *steps = nullptr;    // device [n_ops][n_inst]
     hipGraphExec_t exec = nullptr;
     uint64_t last_use = 0;
@@ -1071,6 +1098,10 @@ scpic_status batch_schedule(scpic_batch *b, const std::vector<std::vector<PassOp
     BatchSchedule s;
     s.key = std::move(key);
     s.shape = ops[0];
+    s.six.assign(n_ops, 0);
+    for (size_t j = 0; j < n_ops; ++j)
+        for (size_t k = 0; k < n; ++k)
+            if (has_thick(ops[k][j].els)) s.six[j] = 1;
     hipError_t e = hipMalloc(&s.steps, sizeof(BatchStep) * std::max<size_t>(1, table.size()));
     if (e != hipSuccess) return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
     if (!table.empty()) {
@@ -1093,8 +1124,8 @@ scpic_status batch_enqueue(scpic_batch *b, hipStream_t s, const scpic_particles 
     for (size_t j = 0; j < sch.shape.size(); ++j) {
         const PassOp &op = sch.shape[j];
         hipError_t e = launch_pass_batched(s, b->launch, all, sch.steps + j * b->n_inst, op.kick,
-                                           b->mixed, op.deposit, b->total_pass_blocks,
-                                           b->pass_threads);
+                                           b->mixed, op.deposit, sch.six[j] != 0,
+                                           b->total_pass_blocks, b->pass_threads);
         if (e != hipSuccess) return fail_hip(e, "batched pass launch");
         if (op.deposit) {
             e = launch_solve_batched(s, b->launch, b->mixed, b->total_rows, b->total_cols,
@@ -1131,14 +1162,17 @@ scpic_status batch_graph(scpic_batch *b, const scpic_particles *parts, BatchSche
 
 // Per-beam op lists of the first turn, a steady turn and the epilogue; they
 // must share one shape (SCPIC_EUNSUPPORTED otherwise).
-scpic_status batch_ops(scpic_batch *b, const scpic_element *const *turns, const int32_t *n_els,
+scpic_status batch_ops(scpic_batch *b, const scpic_particles *parts,
+                       const scpic_element *const *turns, const int32_t *n_els,
                        std::vector<std::vector<PassOp>> &first,
                        std::vector<std::vector<PassOp>> &steady,
                        std::vector<std::vector<PassOp>> &tail, bool &any_sc0)
 {
     for (int k = 0; k < b->n_inst; ++k) {
         std::vector<const scpic_element *> all, trailing;
-        if (scpic_status st = collect_elements(turns[k], n_els[k], all, true)) {
+        scpic_status st = collect_elements(turns[k], n_els[k], all, true);
+        if (!st) st = check_longitudinal(all, parts);
+        if (st) {
             g_last_error = "beam " + std::to_string(k) + ": " + g_last_error;
             return st;
         }
@@ -1204,6 +1238,10 @@ scpic_status scratch_copy(hipStream_t s, const scpic_particles *src, ScratchPart
     dst.p.y = (double *)q;
     if ((st = clone(src->py, 8 * n, &q))) return st;
     dst.p.py = (double *)q;
+    if ((st = clone(src->sigma, 8 * n, &q))) return st;
+    dst.p.sigma = (double *)q;
+    if ((st = clone(src->psigma, 8 * n, &q))) return st;
+    dst.p.psigma = (double *)q;
     if ((st = clone(src->w, 4 * n, &q))) return st;
     dst.p.w = (const float *)q;
     if ((st = clone(src->lost, n, &q))) return st;
@@ -1231,7 +1269,7 @@ scpic_status scpic_batch_autotune(scpic_batch *b, const scpic_particles *parts,
     const int n = b->n_inst;
     std::vector<std::vector<PassOp>> first(n), steady(n), tail(n);
     bool any_sc = false;
-    if (scpic_status st = batch_ops(b, turns, n_els, first, steady, tail, any_sc)) return st;
+    if (scpic_status st = batch_ops(b, parts, turns, n_els, first, steady, tail, any_sc)) return st;
     SCPIC_HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     batch_drop_all_schedules(b);
     ScratchParts scratch;
@@ -1348,7 +1386,7 @@ scpic_status scpic_track_batched(scpic_batch *b, const scpic_particles *parts,
     const int n = b->n_inst;
     std::vector<std::vector<PassOp>> first(n), steady(n), tail(n);
     bool any_sc0 = false;
-    if (scpic_status st = batch_ops(b, turns, n_els, first, steady, tail, any_sc0)) return st;
+    if (scpic_status st = batch_ops(b, parts, turns, n_els, first, steady, tail, any_sc0)) return st;
     if (n_turns == 0 || parts->n == 0) return SCPIC_OK;
     BatchSchedule *sch = nullptr;
     if (!any_sc0) {

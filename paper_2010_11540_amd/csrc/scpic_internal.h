@@ -19,6 +19,9 @@ constexpr double kChargeOne = 16777216.0;  // 2^24
 // Elements a single particle pass can carry in its kernel arguments.
 constexpr int kMaxPassElements = 12;
 
+// Most split steps a thick sextupole may take.
+constexpr int kMaxSextSteps = 1024;
+
 // Largest FFT length (2 * largest grid side) and largest grid.
 constexpr int kMaxFft = 512;
 constexpr int kMaxCells = 65536;
@@ -62,6 +65,8 @@ struct DepositTarget {
 
 struct ParticlePtrs {
     double *x, *px, *y, *py;
+    double *sigma;         // longitudinal pair, may be null (four-dimensional)
+    const double *psigma;
     const float *w;  // per-particle kick weight (2.5D line density), may be null
     uint8_t *lost;
     int64_t n;
@@ -112,11 +117,15 @@ hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, voi
 
 hipError_t prepare_pass_kernels(size_t lds_bytes);
 
+// True when els holds a thick element (the pass then needs sigma, p_sigma).
+bool has_thick(const PassElements &els);
+
 // One particle pass over every beam of a batch (blocks = total pass
-// workgroups of the batch); steps[beam] holds each beam's kick and elements.
+// workgroups of the batch); steps[beam] holds each beam's kick and elements;
+// six when any beam's elements in this pass are thick.
 hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                const BatchStep *steps, bool kick, bool mixed, bool deposit,
-                               int blocks, int threads);
+                               bool six, int blocks, int threads);
 
 // Exact charge grid q (int64) and deposited count from the partials of the
 // last depositing pass (blocks_used workgroups); clears the carry grid.

@@ -43,7 +43,7 @@ class Grid(ctypes.Structure):
 class Particles(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("px", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("py", ctypes.c_void_p), ("w", ctypes.c_void_p), ("lost", ctypes.c_void_p),
-                ("n", ctypes.c_int64)]
+                ("n", ctypes.c_int64), ("sigma", ctypes.c_void_p), ("psigma", ctypes.c_void_p)]
 
 
 class ScpicError(RuntimeError):
@@ -138,7 +138,18 @@ def particles_struct(parts: dict) -> Particles:
         if not (w.is_cuda and w.dtype == torch.float32 and w.is_contiguous() and w.shape == (n,)):
             raise TypeError("w must be a contiguous float32 CUDA tensor of length n")
         wp = w.data_ptr()
-    return Particles(*ptrs, wp, lp, n)
+    longi = []
+    for k in ("sigma", "psigma"):
+        t = parts.get(k)
+        if t is not None:
+            t = _dev_f64(t, k)
+            if t.shape[0] != n or t.device != x.device:
+                raise ValueError(f"{k} must have n entries on the particles' device")
+            t = t.data_ptr()
+        longi.append(t)
+    if (longi[0] is None) != (longi[1] is None):
+        raise ValueError("give both sigma and psigma, or neither")
+    return Particles(*ptrs, wp, lp, n, *longi)
 
 
 def _elements(elements) -> np.ndarray:
