@@ -96,38 +96,107 @@ __device__ __forceinline__ void apply_element(int kind, const double *__restrict
     }
 }
 
-// One transverse plane of the thick quadrupole (Sec. III-B) over length L:
-// u' = q p_u and p_u' = -K u with q = 1 - p_sigma, K = k1 for x and -k1 for y.
-// With w = sqrt|K q|, C = cos(w L) or cosh(w L) and S = sin(w L)/w or
-// sinh(w L)/w (S = L when K = 0), the flow is u <- u C + q p_u S,
-// p_u <- p_u C - K u S.  Returns the integral of p_u^2 over the element, taken
-// from the plane's invariant E = q p_u^2 + K u^2: d(u p_u)/ds = 2 q p_u^2 - E,
-// so the integral is (E L + u(L) p_u(L) - u(0) p_u(0)) / (2 q).
-// cosh and sinh come from one expm1, which keeps sinh accurate at small w L.
-__device__ __forceinline__ double quad_plane(double &u, double &pu, double K, double q, double L)
+// The thick elements below carry no bit-exactness contract (their reference
+// evaluates other, equivalent formulas), so they use fused multiply-adds.
+
+// sin and cos (HYP false) or sinh and cosh (HYP true) of phi0 + d from their
+// values s0, c0 at phi0 and the Taylor series of the functions of d through
+// d^11 and d^10 in Horner form (for |d| <= 1/16 the omitted terms are below
+// 1e-19 of the result).
+template <bool HYP>
+__device__ __forceinline__ void shift_angle(double d, double s0, double c0, double &s, double &c)
+{
+    const double t = HYP ? d * d : -(d * d);
+    double ps = fma(t, 1.0 / 39916800.0, 1.0 / 362880.0);
+    ps = fma(t, ps, 1.0 / 5040.0);
+    ps = fma(t, ps, 1.0 / 120.0);
+    ps = fma(t, ps, 1.0 / 6.0);
+    double pc = fma(t, 1.0 / 3628800.0, 1.0 / 40320.0);
+    pc = fma(t, pc, 1.0 / 720.0);
+    pc = fma(t, pc, 1.0 / 24.0);
+    pc = fma(t, pc, 0.5);
+    const double sd = fma(d * t, ps, d);
+    const double cd = fma(t, pc, 1.0);
+    s = fma(s0, cd, c0 * sd);
+    c = HYP ? fma(c0, cd, s0 * sd) : fma(c0, cd, -(s0 * sd));
+}
+
+// One transverse plane of the thick quadrupole (Sec. III-B): u' = q p_u and
+// p_u' = -K u with q = 1 - p_sigma (K = k1 for x, -k1 for y).  With C the
+// plane's cos or cosh of its angle and sw = (sin or sinh)/sqrt(|K| q), the flow
+// over L is u <- u C + q p_u sw, p_u <- p_u C - K u sw.  Returns the integral of
+// p_u^2 over the element from the plane's invariant E = q p_u^2 + K u^2: since
+// d(u p_u)/ds = 2 q p_u^2 - E, it is (E L + u(L) p_u(L) - u(0) p_u(0)) / (2 q);
+// half_q = 1 / (2 q).
+__device__ __forceinline__ double quad_plane(double &u, double &pu, double K, double q, double L,
+                                             double C, double sw, double half_q)
 {
     const double u0 = u, p0 = pu;
-    const double kq = K * q;
-    double c, sw;
-    if (kq > 0.0) {
-        const double w = sqrt(kq);
-        double sn;
-        sincos(w * L, &sn, &c);
-        sw = sn / w;
-    } else if (kq < 0.0) {
-        const double w = sqrt(-kq);
-        const double em = expm1(w * L);
-        const double e = em + 1.0;
-        c = 0.5 * (e + 1.0 / e);
-        sw = 0.5 * (em + em / e) / w;
+    u = fma(u0, C, q * p0 * sw);
+    pu = fma(p0, C, -(K * u0 * sw));
+    const double inv = fma(q * p0, p0, K * u0 * u0);
+    return fma(inv, L, fma(u, pu, -(u0 * p0))) * half_q;
+}
+
+// Per-particle quantities every thick element of a pass shares: q = 1 - p_sigma,
+// sqrt(q) and 1/sqrt(q).
+struct Chroma {
+    double psg, q, sq, isq;
+};
+
+__device__ __forceinline__ Chroma chroma(double psg)
+{
+    Chroma k;
+    k.psg = psg;
+    k.q = 1.0 - psg;
+    k.sq = sqrt(k.q);
+    k.isq = 1.0 / k.sq;
+    return k;
+}
+
+// Thick quadrupole with chromatic focusing (Sec. III-B).  Both planes turn by
+// phi = sqrt(|k1| q) L = phi0 sqrt(q): trigonometric functions in the
+// focusing plane, hyperbolic in the other.  The host supplies phi0 and the
+// four functions at phi0 (m[3..7]) and 1/sqrt|k1| (m[8]); a particle's
+// functions follow from the offset d = phi - phi0 = phi0 (sqrt(q) - 1) by the
+// addition formulas (|d| <= 1/16, i.e. any momentum spread of a real beam), or
+// directly from phi beyond that.  Then
+//   sigma += p_sigma L / gamma0^2 - (1/2) int (px^2 + py^2) ds.
+__device__ __forceinline__ void quad_thick(const double *__restrict__ m, double &x, double &px,
+                                           double &y, double &py, double &sg, const Chroma &k)
+{
+    const double k1 = m[0], L = m[1], ig2 = m[2];
+    const double q = k.q;
+    double ix, iy;
+    if (k1 == 0.0) {
+        ix = px * px * L;
+        iy = py * py * L;
+        x = fma(q * px, L, x);
+        y = fma(q * py, L, y);
     } else {
-        c = 1.0;
-        sw = L;
+        const double phi0 = m[3], d = phi0 * (k.sq - 1.0);
+        double s, c, sh, ch;
+        if (fabs(d) <= 0.0625) {
+            shift_angle<false>(d, m[4], m[5], s, c);
+            shift_angle<true>(d, m[6], m[7], sh, ch);
+        } else {
+            const double phi = phi0 * k.sq;
+            sincos(phi, &s, &c);
+            const double em = expm1(phi), e = em + 1.0;
+            ch = 0.5 * (e + 1.0 / e);
+            sh = 0.5 * (em + em / e);
+        }
+        const double iw = m[8] * k.isq;  // 1 / sqrt(|k1| q)
+        const double half_q = 0.5 * k.isq * k.isq;
+        if (k1 > 0.0) {
+            ix = quad_plane(x, px, k1, q, L, c, s * iw, half_q);
+            iy = quad_plane(y, py, -k1, q, L, ch, sh * iw, half_q);
+        } else {
+            ix = quad_plane(x, px, k1, q, L, ch, sh * iw, half_q);
+            iy = quad_plane(y, py, -k1, q, L, c, s * iw, half_q);
+        }
     }
-    u = u0 * c + q * p0 * sw;
-    pu = p0 * c - K * u0 * sw;
-    const double inv = q * p0 * p0 + K * u0 * u0;
-    return (inv * L + u * pu - u0 * p0) / (2.0 * q);
+    sg = sg + fma(k.psg * ig2, L, -0.5 * (ix + iy));
 }
 
 // One element applied to one particle in six dimensions (Sec. III): the
@@ -138,33 +207,35 @@ __device__ __forceinline__ double quad_plane(double &u, double &pu, double K, do
 // flows of H0 = (px^2 + py^2)(1 - p_sigma)/2 + p_sigma^2/(2 gamma0^2) and of
 // V = k2 (x^3 - 3 x y^2)/6 over the step h = L/n:
 //   H0 (a h), V (h/2), H0 (c h), V (h/2), H0 (a h),  c = 1/sqrt 3, a = (1 - c)/2.
-// p_sigma is constant in every element.
+// k2 = 0 takes the drift in one step.  p_sigma is constant in every element.
 __device__ __forceinline__ void apply_element6(int kind, const double *__restrict__ m, double &x,
                                                double &px, double &y, double &py, double &sg,
-                                               double psg)
+                                               const Chroma &k)
 {
     if (kind == SCPIC_EL_QUAD_THICK) {
-        const double k1 = m[0], L = m[1], ig2 = m[2];
-        const double q = 1.0 - psg;
-        const double ix = quad_plane(x, px, k1, q, L);
-        const double iy = quad_plane(y, py, -k1, q, L);
-        sg = sg + (psg * ig2 * L - 0.5 * (ix + iy));
+        quad_thick(m, x, px, y, py, sg, k);
+    } else if (kind == SCPIC_EL_SEXT_THICK && m[0] == 0.0) {
+        // no sextupole field: the split composes to the exact drift of H0
+        const double L = m[1];
+        sg = fma(fma(-0.5 * px, px, fma(-0.5 * py, py, k.psg * m[2])), L, sg);
+        x = fma(px * k.q, L, x);
+        y = fma(py * k.q, L, y);
     } else if (kind == SCPIC_EL_SEXT_THICK) {
         constexpr double kC = 0.57735026918962576451;  // 1/sqrt(3)
         constexpr double kA = 0.5 * (1.0 - kC);
         const int n = (int)m[3];
         const double h = m[1] / (double)n;
-        const double q = 1.0 - psg, dsg = psg * m[2];
+        const double dsg = k.psg * m[2];
         const double ta = kA * h, tc = kC * h, tv = 0.5 * h * m[0];
         auto drift = [&](double t) {
-            x = x + px * q * t;
-            y = y + py * q * t;
-            sg = sg + (dsg - 0.5 * (px * px + py * py)) * t;
+            x = fma(px * k.q, t, x);
+            y = fma(py * k.q, t, y);
+            sg = fma(fma(-0.5 * px, px, fma(-0.5 * py, py, dsg)), t, sg);
         };
         auto kick = [&]() {
             const double X = x, Y = y;
-            px = px - 0.5 * tv * (X * X - Y * Y);
-            py = py + tv * X * Y;
+            px = fma(-0.5 * tv, fma(X, X, -(Y * Y)), px);
+            py = fma(tv * X, Y, py);
         };
         for (int i = 0; i < n; ++i) {
             drift(ta);
@@ -441,8 +512,9 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         }
         if (act) {
             if constexpr (SIX) {
+                const Chroma ck = chroma(psg);
                 for (int e = 0; e < els.n_el; ++e)
-                    apply_element6(els.kind[e], els.p[e], x, px, y, py, sg, psg);
+                    apply_element6(els.kind[e], els.p[e], x, px, y, py, sg, ck);
             } else {
                 for (int e = 0; e < els.n_el; ++e)
                     apply_element(els.kind[e], els.p[e], x, px, y, py);

@@ -207,8 +207,21 @@ PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, siz
     std::memset(&pe, 0, sizeof(pe));
     pe.n_el = (int32_t)(end - begin);
     for (size_t i = begin; i < end; ++i) {
+        double *m = pe.p[i - begin];
         pe.kind[i - begin] = v[i]->kind;
-        std::memcpy(pe.p[i - begin], v[i]->p, sizeof(double) * 16);
+        std::memcpy(m, v[i]->p, sizeof(double) * 16);
+        if (v[i]->kind == SCPIC_EL_QUAD_THICK) {
+            // the on-momentum rotation of both planes, which the kernel
+            // corrects per particle for its p_sigma
+            const double w0 = std::sqrt(std::fabs(m[0])), phi0 = w0 * m[1];
+            m[3] = phi0;
+            m[4] = std::sin(phi0);
+            m[5] = std::cos(phi0);
+            m[6] = std::sinh(phi0);
+            m[7] = std::cosh(phi0);
+            m[8] = w0 > 0.0 ? 1.0 / w0 : 0.0;
+            for (int k = 9; k < 16; ++k) m[k] = 0.0;
+        }
     }
     return pe;
 }

@@ -45,7 +45,9 @@ struct GridGeom {
 };
 
 // Elements of one pass, passed by value in the kernel arguments (read with
-// scalar loads, uniform across the wave).
+// scalar loads, uniform across the wave).  A thick quadrupole's p[3..8] hold
+// values derived on the host from k1 and L: phi0 = sqrt|k1| L, sin, cos,
+// sinh and cosh of phi0, and 1/sqrt|k1| (0 when k1 = 0).
 struct PassElements {
     int32_t n_el;
     int32_t kind[kMaxPassElements];

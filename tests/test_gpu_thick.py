@@ -73,17 +73,24 @@ def _thick_mix():
 
 
 @pytest.mark.parametrize("case,n", [("mix", 10_007), ("mix", 1), ("mix", 300_001),
-                                    ("fodo", 100_003)])
+                                    ("fodo", 100_003), ("wide", 50_001)])
 def test_thick_push_matches_oracle(gpu, orc, case, n):
     """mix: one push through every thick form (the mix is not a stable ring:
     one pass only); fodo: three turns of the thick FODO ring with 3-step
-    sextupoles."""
+    sextupoles; wide: the mix with a momentum spread (p_sigma rms 0.15) so wide
+    that many particles' quadrupole angles differ from the on-momentum angle
+    by more than 1/16 rad, the limit of the kernel's short-series path."""
     _say(f"push {n} particles through {case}")
-    if case == "mix":
+    if case in ("mix", "wide"):
         lat, reps = _thick_mix(), 1
     else:
         lat, reps = inputs.fodo_thick(16, 4.2, None, sext_steps=3), 3
-    p0 = inputs.gaussian_beam6d(n, 40 + n, sigma_ps=3e-3)
+    p0 = inputs.gaussian_beam6d(n, 40 + n, sigma_ps=0.15 if case == "wide" else 3e-3)
+    if case == "wide":
+        quads = lat[lat["kind"] == inputs.QUAD_THICK]
+        phi0 = np.sqrt(np.abs(quads["p"][:, 0])) * quads["p"][:, 1]
+        d = np.abs(phi0[:, None] * (np.sqrt(1.0 - p0["psigma"][None, :]) - 1.0))
+        assert (d > 1 / 16).mean() > 0.05 and (d <= 1 / 16).mean() > 0.5
     ref = inputs.copy_parts(p0)
     for _ in range(reps):
         orc.push(ref, lat)
