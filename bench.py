@@ -33,6 +33,26 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64  # read + write x, px, y, py in FP64
 BYTES_PER_WEIGHT = 4          # + the FP32 line-density kick weight (2.5D long bunch)
 BYTES_PER_LONGITUDINAL = 24   # + read sigma, p_sigma and write sigma (thick elements, 6D)
+FP64_PEAK_TFLOPS = 78.6       # MI355X vector FP64
+# FP64 operations per particle (a fused multiply-add counts 2, sqrt and
+# division 1) of the pass's arithmetic: gather + kick and the deposit's cell
+# and weights, plus each element of the pass
+FLOPS_KICK, FLOPS_DEPOSIT, FLOPS_CHROMA = 35, 14, 3
+
+
+def element_flops(e, inputs) -> int:
+    k, m = int(e["kind"]), e["p"]
+    if k == inputs.LIN2X2:
+        return 12
+    if k == inputs.LIN4X4:
+        return 28
+    if k == inputs.SEXT_THIN:
+        return 8
+    if k == inputs.QUAD_THICK:
+        return 105 if m[0] != 0.0 else 16
+    if k == inputs.SEXT_THICK:
+        return 15 if m[0] == 0.0 else 6 + 60 * int(m[3])
+    return 0
 PROFILE_TRAFFIC = ROOT / "profiles" / "pass_traffic_production.json"
 PASS_SOURCE = ROOT / "paper_2010_11540_amd" / "csrc" / "particles.hip"
 
@@ -359,6 +379,17 @@ def main():
         "avg_launch_us": round(pass_us, 3),
         "grid_phase_us": round(grid_us, 3),
     }
+    if six:
+        # thick elements make the pass arithmetic-bound: FP64 roofline, with
+        # the HBM figures kept beside it
+        flops = (FLOPS_KICK + FLOPS_DEPOSIT + FLOPS_CHROMA
+                 + sum(element_flops(e, inputs) for e in one_map))
+        tflops = flops * n / (pass_us * 1e-6) / 1e12
+        roofline.update({
+            "bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+            "flops_per_particle": flops, "hbm_achieved_gbs": round(achieved, 1),
+            "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)})
     del d2
 
     cpu = None
