@@ -26,6 +26,13 @@ What each function follows (arXiv:2010.11540):
   kick        Sec. IV: transverse kick proportional to the field at the
               particle times the distance since the previous kick, and (2.5D
               form) to the line density at the particle relative to its peak.
+  line        Sec. IV: the line density lambda(sigma) as a histogram of sigma
+              (the one-dimensional form of the charge assignment), recomputed
+              at every space-charge step; the transverse kick scaled by
+              lambda/lambda_peak and the longitudinal kick
+              -gamma0 kappa phi lambda'/lambda_peak (the two printed kick
+              coefficients differ by gamma0), with phi the grounded-pipe
+              potential (Sec. IV-B).
 """
 from __future__ import annotations
 
@@ -88,6 +95,17 @@ def lib():
         L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
                                 i32, vp, vp, i32, i32]
         L.orc_track.restype = i32
+        L.orc_deposit_line.argtypes = [i64, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, dbl,
+                                       dbl, vp, vp]
+        L.orc_deposit_line.restype = i64
+        L.orc_line_table.argtypes = [vp, i32, dbl, vp, vp]
+        L.orc_line_table.restype = None
+        L.orc_space_charge_line.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl,
+                                            dbl, i32, dbl, dbl, dbl, dbl, dbl, vp, vp, vp]
+        L.orc_space_charge_line.restype = i64
+        L.orc_track_line.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
+                                     i32, dbl, dbl, dbl, i32, vp, vp, i32]
+        L.orc_track_line.restype = i32
         _lib = L
     return _lib
 
@@ -227,3 +245,65 @@ def track(parts: dict, grid, elements, n_turns: int, solver: str = "open") -> No
                          _ptr(par), int(n_turns), _pipe(solver))
     if rc != 0:
         raise ValueError("thick elements need sigma and psigma, and n >= 1 sextupole steps")
+
+
+def _line_args(line):
+    return int(line["nz"]), float(line["z_min"]), float(line["dz"])
+
+
+def deposit_line(parts: dict, grid, line) -> tuple[np.ndarray, np.ndarray, int]:
+    """Transverse charge q (nx*ny) and line histogram h (nz, 4096 units per
+    particle) of the particles inside both domains; the others are marked lost."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    q = np.zeros(nx * ny, dtype=np.int64)
+    h = np.zeros(int(line["nz"]), dtype=np.int64)
+    n = parts["x"].shape[0]
+    n_in = lib().orc_deposit_line(n, _ptr(parts["x"]), _ptr(parts["y"]), _ptr(_f64(parts["sigma"])),
+                                  _ptr(parts.get("lost")), *_grid_args(grid), *_line_args(line),
+                                  _ptr(q), _ptr(h))
+    return q, h, int(n_in)
+
+
+def line_table(h: np.ndarray, line) -> tuple[np.ndarray, np.ndarray]:
+    """(lambda/lambda_peak, lambda'/lambda_peak) at the line's nodes."""
+    h = np.ascontiguousarray(h, dtype=np.int64)
+    nz = int(line["nz"])
+    lw, ld = np.zeros(nz), np.zeros(nz)
+    lib().orc_line_table(_ptr(h), nz, float(line["dz"]), _ptr(lw), _ptr(ld))
+    return lw, ld
+
+
+def space_charge_line(parts: dict, grid, line, scale: float, kappa: float):
+    """One long-bunch space-charge step in place (grounded pipe); returns
+    (lw, ld, phi, n_in) with phi as potential(..., solver="pipe")."""
+    nx, ny = int(grid["nx"]), int(grid["ny"])
+    nz = int(line["nz"])
+    lw, ld = np.zeros(nz), np.zeros(nz)
+    phi = np.zeros((nx + 2) * (ny + 2))
+    n = parts["x"].shape[0]
+    sp, psp = _longitudinal(parts)
+    if sp is None or psp is None:
+        raise ValueError("the line-density step needs sigma and psigma")
+    n_in = lib().orc_space_charge_line(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                                       _ptr(parts["py"]), sp, psp, _ptr(parts.get("lost")),
+                                       *_grid_args(grid), *_line_args(line), float(line["gamma0"]),
+                                       float(scale), float(kappa), _ptr(lw), _ptr(ld), _ptr(phi))
+    if n_in < 0:
+        raise MemoryError("oracle line step: allocation failed")
+    return lw, ld, phi.reshape(nx + 2, ny + 2), int(n_in)
+
+
+def track_line(parts: dict, grid, line, elements, n_turns: int) -> None:
+    """In place: n_turns with the long-bunch space-charge step (grounded pipe)
+    at every SC element."""
+    kind, par = _elements(elements)
+    n = parts["x"].shape[0]
+    sp, psp = _longitudinal(parts)
+    if sp is None or psp is None:
+        raise ValueError("the line-density step needs sigma and psigma")
+    rc = lib().orc_track_line(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                              _ptr(parts["py"]), sp, psp, _ptr(parts.get("lost")),
+                              *_grid_args(grid), *_line_args(line), float(line["gamma0"]),
+                              len(kind), _ptr(kind), _ptr(par), int(n_turns))
+    if rc != 0:
+        raise ValueError("bad sextupole steps or out of memory")

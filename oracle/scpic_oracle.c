@@ -522,6 +522,185 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
     return n_in;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Longitudinal space charge of a long bunch (Sec. IV): the line density     */
+/* lambda(sigma) from a histogram of sigma, the transverse kick scaled by     */
+/* lambda / lambda_peak and the longitudinal kick from the potential.        */
+/* ------------------------------------------------------------------------ */
+
+/* Node k and the two fixed-point weights of sigma on the line of nz nodes
+ * z_min + k dz: t = (s - z_min)(1/dz), k = floor(t), a = floor((t - k) 4096 + 0.5),
+ * weights 4096 - a at node k and a at node k + 1 (the one-dimensional form of
+ * the transverse assignment).  Returns 0 outside [z_min, z_min + (nz-1) dz). */
+static int line_weights(double s, int nz, double z_min, double inv_dz, int *k, int64_t w[2])
+{
+    double t = (s - z_min) * inv_dz;
+    if (!(t >= 0.0 && t < (double)(nz - 1))) return 0;
+    double fk = floor(t);
+    int64_t a = (int64_t)floor((t - fk) * 4096.0 + 0.5);
+    *k = (int)fk;
+    w[0] = ORC_FRAC_ONE - a;
+    w[1] = a;
+    return 1;
+}
+
+/* Transverse charge q (as orc_deposit, nx*ny) and line-density histogram h
+ * (nz nodes, 4096 units per particle) of the particles inside both domains;
+ * a particle outside either is marked lost and deposits nothing.  Returns the
+ * number deposited. */
+int64_t orc_deposit_line(int64_t n, const double *x, const double *y, const double *sigma,
+                         uint8_t *lost, int nx, int ny, double x_min, double y_min, double dx,
+                         double dy, int nz, double z_min, double dz, int64_t *q, int64_t *h)
+{
+    orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+    double inv_dz = 1.0 / dz;
+    memset(q, 0, sizeof(int64_t) * (size_t)nx * ny);
+    memset(h, 0, sizeof(int64_t) * (size_t)nz);
+    int64_t n_in = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        if (lost && lost[p]) continue;
+        int i, j, k;
+        int64_t w[4], wl[2];
+        if (!cic_weights(&g, x[p], y[p], &i, &j, w) ||
+            !line_weights(sigma[p], nz, z_min, inv_dz, &k, wl)) {
+            if (lost) lost[p] = 1;
+            continue;
+        }
+        q[(int64_t)i * ny + j] += w[0];
+        q[(int64_t)(i + 1) * ny + j] += w[1];
+        q[(int64_t)i * ny + j + 1] += w[2];
+        q[(int64_t)(i + 1) * ny + j + 1] += w[3];
+        h[k] += wl[0];
+        h[k + 1] += wl[1];
+        n_in += 1;
+    }
+    return n_in;
+}
+
+/* Line-density factors at the nodes, relative to the peak:
+ *   lw[k] = h[k] / max h,   ld[k] = (h[k+1] - h[k-1]) / (2 dz max h)
+ * (centred difference, h = 0 beyond the line; all zero for an empty line). */
+void orc_line_table(const int64_t *h, int nz, double dz, double *lw, double *ld)
+{
+    int64_t hmax = 0;
+    for (int k = 0; k < nz; ++k)
+        if (h[k] > hmax) hmax = h[k];
+    for (int k = 0; k < nz; ++k) {
+        if (hmax == 0) {
+            lw[k] = 0.0;
+            ld[k] = 0.0;
+            continue;
+        }
+        int64_t up = k + 1 < nz ? h[k + 1] : 0, down = k > 0 ? h[k - 1] : 0;
+        lw[k] = (double)h[k] / (double)hmax;
+        ld[k] = (double)(up - down) / (2.0 * dz * (double)hmax);
+    }
+}
+
+/* One space-charge step of a long bunch in the grounded rectangular pipe
+ * (Sec. IV with the solver of Sec. IV-B): deposit (transverse charge and line
+ * density), pipe potential phi and field E, then for every particle, with
+ * w = lambda(sigma)/lambda_peak and d = lambda'(sigma)/lambda_peak
+ * interpolated from the node factors with its line weights, and phi, E
+ * interpolated with its transverse weights:
+ *   px += kappa w Ex,  py += kappa w Ey,  p_sigma -= gamma0 kappa phi d.
+ * The longitudinal kick's coefficient e/(m gamma0^2 beta0^2 c^2) is gamma0
+ * times the transverse one, e/(m gamma0^3 beta0^2 c^2), which kappa carries.
+ * lw_out, ld_out (nz) and phi_out ((nx+2)(ny+2), as orc_potential_pipe)
+ * receive the tables when not NULL.  Returns the number deposited, -1 when out
+ * of memory. */
+int64_t orc_space_charge_line(int64_t n, double *x, double *px, double *y, double *py,
+                              const double *sigma, double *psigma, uint8_t *lost, int nx, int ny,
+                              double x_min, double y_min, double dx, double dy, int nz,
+                              double z_min, double dz, double gamma0, double scale, double kappa,
+                              double *lw_out, double *ld_out, double *phi_out)
+{
+    int64_t cells = (int64_t)nx * ny;
+    int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)cells);
+    int64_t *h = (int64_t *)malloc(sizeof(int64_t) * (size_t)nz);
+    double *phi = (double *)malloc(sizeof(double) * (size_t)(nx + 2) * (ny + 2));
+    double *ex = (double *)malloc(sizeof(double) * (size_t)cells);
+    double *ey = (double *)malloc(sizeof(double) * (size_t)cells);
+    double *lw = (double *)malloc(sizeof(double) * (size_t)nz);
+    double *ld = (double *)malloc(sizeof(double) * (size_t)nz);
+    int64_t n_in = -1;
+    if (!q || !h || !phi || !ex || !ey || !lw || !ld) goto done;
+    n_in = orc_deposit_line(n, x, y, sigma, lost, nx, ny, x_min, y_min, dx, dy, nz, z_min, dz, q,
+                            h);
+    orc_potential_pipe(q, scale, nx, ny, dx, dy, phi);
+    orc_field(phi, nx, ny, dx, dy, ex, ey);
+    orc_line_table(h, nz, dz, lw, ld);
+    {
+        orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+        double inv_dz = 1.0 / dz;
+        int64_t p;
+#pragma omp parallel for schedule(static)
+        for (p = 0; p < n; ++p) {
+            if (lost && lost[p]) continue;
+            int i, j, k;
+            int64_t w[4], wl[2];
+            if (!cic_weights(&g, x[p], y[p], &i, &j, w) ||
+                !line_weights(sigma[p], nz, z_min, inv_dz, &k, wl)) {
+                if (lost) lost[p] = 1;
+                continue;
+            }
+            int64_t c00 = (int64_t)i * ny + j, c10 = c00 + ny, c01 = c00 + 1, c11 = c00 + ny + 1;
+            int64_t s = ny + 2, f00 = (int64_t)(i + 1) * s + (j + 1);
+            double exp_ = ((double)w[0] * ex[c00] + (double)w[1] * ex[c10] +
+                           (double)w[2] * ex[c01] + (double)w[3] * ex[c11]) / ORC_CHARGE_ONE;
+            double eyp = ((double)w[0] * ey[c00] + (double)w[1] * ey[c10] +
+                          (double)w[2] * ey[c01] + (double)w[3] * ey[c11]) / ORC_CHARGE_ONE;
+            double php = ((double)w[0] * phi[f00] + (double)w[1] * phi[f00 + s] +
+                          (double)w[2] * phi[f00 + 1] + (double)w[3] * phi[f00 + s + 1]) /
+                         ORC_CHARGE_ONE;
+            double wp = ((double)wl[0] * lw[k] + (double)wl[1] * lw[k + 1]) / ORC_FRAC_ONE;
+            double dp = ((double)wl[0] * ld[k] + (double)wl[1] * ld[k + 1]) / ORC_FRAC_ONE;
+            px[p] += kappa * wp * exp_;
+            py[p] += kappa * wp * eyp;
+            psigma[p] -= gamma0 * kappa * php * dp;
+        }
+    }
+    if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)nz);
+    if (ld_out) memcpy(ld_out, ld, sizeof(double) * (size_t)nz);
+    if (phi_out) memcpy(phi_out, phi, sizeof(double) * (size_t)(nx + 2) * (ny + 2));
+done:
+    free(q);
+    free(h);
+    free(phi);
+    free(ex);
+    free(ey);
+    free(lw);
+    free(ld);
+    return n_in;
+}
+
+/* Tracking of a long bunch: as orc_track with the grounded pipe, every
+ * space-charge element running orc_space_charge_line on the line of nz nodes
+ * from z_min with spacing dz.  Returns -1 (nothing tracked) under the
+ * conditions orc_push rejects, or when out of memory. */
+int orc_track_line(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
+                   double *psigma, uint8_t *lost, int nx, int ny, double x_min, double y_min,
+                   double dx, double dy, int nz, double z_min, double dz, double gamma0,
+                   int n_el, const int32_t *kind, const double *par, int n_turns)
+{
+    double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
+    if (!sigma || !psigma) return -1;
+    for (int e = 0; e < n_el; ++e)
+        if (kind[e] == ORC_SEXT_THICK && par[16 * e + 3] < 1.0) return -1;
+    for (int t = 0; t < n_turns; ++t)
+        for (int e = 0; e < n_el; ++e) {
+            if (kind[e] == ORC_SC) {
+                if (orc_space_charge_line(n, x, px, y, py, sigma, psigma, lost, nx, ny, x_min,
+                                          y_min, dx, dy, nz, z_min, dz, gamma0, scale,
+                                          par[16 * e], NULL, NULL, NULL) < 0)
+                    return -1;
+            } else {
+                orc_push(n, x, px, y, py, sigma, psigma, lost, 1, kind + e, par + 16 * e);
+            }
+        }
+    return 0;
+}
+
 /* Track n_turns through the element sequence of one turn: non-space-charge
  * elements are pushed, each space-charge element runs the full step above with
  * its own kappa.  The charge scale is 1/(2^24 n): n is the initial particle

@@ -258,6 +258,14 @@ def ring(qx: float, qy: float, n_seg: int, kappa: float, beta: float = 1.0,
     return np.concatenate(parts)
 
 
+def make_line(half: float, nz: int = 128, gamma0: float | None = None) -> dict:
+    """Line-density grid of nz nodes spanning [-half, half] in sigma (the
+    paper's 128-bin line density, Sec. IV), with the reference gamma0 of the
+    longitudinal kick."""
+    return {"nz": int(nz), "z_min": -half, "dz": 2.0 * half / (nz - 1),
+            "gamma0": GAMMA0_3GEV if gamma0 is None else float(gamma0)}
+
+
 # 3 GeV kinetic energy protons (the Main Ring's injection energy)
 GAMMA0_3GEV = 1.0 + 3.0 / PROTON_MASS_GEV
 
