@@ -38,6 +38,10 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X vector FP64
 # division 1) of the pass's arithmetic: gather + kick and the deposit's cell
 # and weights, plus each element of the pass
 FLOPS_KICK, FLOPS_DEPOSIT, FLOPS_CHROMA = 35, 14, 3
+# the line density: line weights at the kick and the deposit, the two table
+# gathers, the potential gather and the longitudinal kick
+FLOPS_LINE = 32
+BYTES_LINE_KICK = 8           # + write p_sigma (the longitudinal kick)
 
 
 def element_flops(e, inputs) -> int:
@@ -67,7 +71,7 @@ def parse():
                     help="untimed SC steps before timing (default: 200 for production, 2 turns "
                          "otherwise)")
     ap.add_argument("--workload", default="production",
-                    choices=["production", "small", "large", "batch", "thick"],
+                    choices=["production", "small", "large", "batch", "thick", "line"],
                     help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
                          "bunch with line-density kick weights, 256^2; batch: 64-beam tune scan")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -132,7 +136,10 @@ def cpu_baseline(w, seconds: float, solver: str = "open"):
     steps = 0
     t0 = time.perf_counter()
     while True:
-        oracle.track(parts, w["grid"], chunk, 1, solver=solver)
+        if "line" in w:
+            oracle.track_line(parts, w["grid"], w["line"], chunk, 1)
+        else:
+            oracle.track(parts, w["grid"], chunk, 1, solver=solver)
         steps += chunk_steps
         el = time.perf_counter() - t0
         if el >= seconds:
@@ -153,6 +160,10 @@ WORKLOAD_TEXT = {
     "small": "small 2D PIC: 1e4 Gaussian particles, 64x64 grid, 16 SC steps/turn",
     "large": ("large 2.5D PIC: 1e7 KV 2:1 long-bunch particles with 128-bin line-density kick "
               "weights, 256x256 grid, 200 SC steps/turn"),
+    "line": ("long-bunch 6D PIC: 1e6 Gaussian particles (x, px, y, py, sigma, p_sigma), 128x128 "
+             "grounded pipe, 128-node line density of sigma recomputed every SC step "
+             "(transverse kick scaled by lambda/lambda_peak, longitudinal kick), per turn 100 thick "
+             "FODO cells, 100 SC steps"),
     "thick": ("6D thick-element PIC: 1e6 Gaussian particles (x, px, y, py, sigma, p_sigma), "
               "128x128 grid, per turn 100 FODO cells of 3 chromatic thick quadrupoles + 2 SABA2 "
               "thick sextupoles + 4 drifts, 100 SC steps"),
@@ -301,8 +312,12 @@ def main():
         sys.exit(2)
     n = w["n"]
     ctx = scpic.Context(w["grid"], args.precision)
+    if "solver" in w:
+        args.solver = w["solver"]
     if args.solver == "pipe":
         ctx.set_option(scpic.OPT_SOLVER, scpic.SOLVER_PIPE)
+    if "line" in w:
+        ctx.set_line_density(w["line"])
     if args.no_graph:
         ctx.set_option(scpic.OPT_USE_GRAPH, 0)
     if args.pass_threads:
@@ -362,14 +377,19 @@ def main():
     torch.cuda.synchronize()
     grid_us = g0.elapsed_time(g1) * 1e3 / args.pass_reps
     six = "sigma" in d and bool(np.isin(one_map["kind"], (inputs.QUAD_THICK, inputs.SEXT_THICK)).any())
+    line_on = "line" in w
+    six = six or line_on
     unit_bytes = (BYTES_PER_PARTICLE_STEP + (BYTES_PER_WEIGHT if "w" in d else 0)
-                  + (BYTES_PER_LONGITUDINAL if six else 0))
+                  + (BYTES_PER_LONGITUDINAL if six else 0) + (BYTES_LINE_KICK if line_on else 0))
     achieved = unit_bytes * n / (pass_us * 1e-6) / 1e9
-    seg = {"production": "4x4 map", "thick": "FODO cell of thick elements"}.get(args.workload, "2x2 map")
+    seg = {"production": "4x4 map", "thick": "FODO cell of thick elements",
+           "line": "FODO cell of thick elements, line density"}.get(args.workload, "2x2 map")
     roofline = {
         "bound": "hbm",
-        "kernel": (f"k_pass<{'double' if args.precision == 'fp64' else 'float'},kick,deposit"
-                   f"{',six' if six else ''}> (gather+kick, {seg}, CIC deposit, flush)"),
+        "kernel": (f"k_pass{'_line' if line_on else ''}<"
+                   f"{'double' if args.precision == 'fp64' else 'float'},kick,deposit"
+                   f"{',six' if six and not line_on else ''}> (gather+kick, {seg}, CIC deposit, "
+                   "flush)"),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -382,7 +402,7 @@ def main():
     if six:
         # thick elements make the pass arithmetic-bound: FP64 roofline, with
         # the HBM figures kept beside it
-        flops = (FLOPS_KICK + FLOPS_DEPOSIT + FLOPS_CHROMA
+        flops = (FLOPS_KICK + FLOPS_DEPOSIT + FLOPS_CHROMA + (FLOPS_LINE if line_on else 0)
                  + sum(element_flops(e, inputs) for e in one_map))
         tflops = flops * n / (pass_us * 1e-6) / 1e12
         roofline.update({

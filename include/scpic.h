@@ -250,6 +250,39 @@ scpic_status scpic_reduce_solve(scpic_ctx *ctx, double scale);
  * scpic_reduce_solve) to ex, ey (device; double or float per precision). */
 scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey);
 
+/* Long-bunch line density (Sec. IV).  nz > 0 turns it on for scpic_track and
+ * scpic_pass / scpic_reduce_solve (the per-element calls scpic_deposit,
+ * scpic_solve and scpic_kick stay transverse); nz = 0 turns it off.  At every
+ * space-charge step the line density lambda(sigma) is histogrammed on the nz
+ * nodes z_min + k dz with the one-dimensional form of the charge assignment
+ * (t = (sigma - z_min)(1/dz), k = floor(t), a = floor((t - k) 4096 + 0.5),
+ * weights 4096 - a at k and a at k + 1, exact integer sums), together with the
+ * transverse charge; the node tables are
+ *   lw[k] = h[k] / max h,   ld[k] = (h[k+1] - h[k-1]) / (2 dz max h)
+ * (h = 0 beyond the line).  Each kick then, with w and d interpolated from lw
+ * and ld with the particle's line weights and phi, E with its transverse
+ * weights, applies
+ *   px += kappa w Ex,  py += kappa w Ey,  p_sigma -= gamma0 kappa phi d:
+ * the transverse kick scaled by lambda(sigma)/lambda_peak and the longitudinal
+ * kick of Sec. IV, whose coefficient e/(m gamma0^2 beta0^2 c^2) is gamma0 times
+ * the transverse one (carried by kappa).  phi is the potential of the grounded
+ * pipe: the line density needs SCPIC_SOLVER_PIPE (SCPIC_EUNSUPPORTED at track
+ * time otherwise), the particles' sigma and psigma, and no per-particle
+ * weights w (SCPIC_EINVAL).  A particle whose sigma leaves [z_min,
+ * z_min + (nz-1) dz) is lost like one leaving the grid.
+ * nz in [8, 512], dz > 0, gamma0 >= 1, all finite.  This call synchronises the
+ * context's stream and allocates the line's buffers (the histograms of up to
+ * the context's largest workgroup count, the node tables, the node potential
+ * and one spectrum); tracking allocates nothing. */
+scpic_status scpic_set_line_density(scpic_ctx *ctx, int32_t nz, double z_min, double dz,
+                                    double gamma0);
+
+/* Copy the line state of the last solve: the node potential phi (device,
+ * nx*ny, double or float per precision, row-major) and the node tables lw, ld
+ * (device, nz doubles each); any pointer may be NULL.  SCPIC_EINVAL when the
+ * line density is off. */
+scpic_status scpic_get_line_state(scpic_ctx *ctx, void *phi, double *lw, double *ld);
+
 /* ---- batches of independent beams --------------------------------------
  * Many independent beams (a tune scan, Sec. V; beams of different sizes on
  * different grids) tracked together: every particle pass and every grid

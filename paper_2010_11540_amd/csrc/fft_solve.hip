@@ -282,12 +282,65 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
     }
 }
 
+// Line density of a long bunch (Sec. IV): sum the nblocks per-workgroup
+// histograms of the last depositing pass exactly and write the node tables
+//   lw[k] = h[k] / max h,   ld[k] = (h[k+1] - h[k-1]) / (2 dz max h)
+// (h = 0 beyond the line; all zero for an empty line).  NT / nz groups of
+// threads split the workgroups; acc is NT words of dynamic LDS.
+template <int NT>
+__device__ __forceinline__ void line_table_body(const LineSpec &L, int nblocks)
+{
+    extern __shared__ unsigned char smem_raw[];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
+    __shared__ unsigned long long wmax[NT / 64];
+    const int tid = threadIdx.x, nz = L.nz;
+    const int groups = NT / nz;
+    const int k = tid % nz, g = tid / nz;
+    unsigned long long s = 0;
+    if (g < groups)
+        for (int b = g; b < nblocks; b += groups) s += L.partial[(size_t)b * nz + k];
+    acc[tid] = s;
+    __syncthreads();
+    unsigned long long h = 0;
+    if (tid < nz)
+        for (int r = 0; r < groups; ++r) h += acc[r * nz + tid];
+    __syncthreads();
+    if (tid < nz) acc[tid] = h;
+    unsigned long long m = h;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = __shfl_xor(m, o, 64);
+        m = v > m ? v : m;
+    }
+    if ((tid & 63) == 0) wmax[tid >> 6] = m;
+    __syncthreads();
+    unsigned long long hmax = 0;
+    for (int w = 0; w < NT / 64; ++w) hmax = wmax[w] > hmax ? wmax[w] : hmax;
+    if (tid < nz) {
+        double lw = 0.0, ld = 0.0;
+        if (hmax) {
+            const long long up = tid + 1 < nz ? (long long)acc[tid + 1] : 0;
+            const long long down = tid > 0 ? (long long)acc[tid - 1] : 0;
+            lw = (double)h / (double)hmax;
+            ld = (double)(up - down) / (2.0 * L.dz * (double)hmax);
+        }
+        L.lw[tid] = lw;
+        L.ld[tid] = ld;
+    }
+}
+
+// Rows of the charge grid; with a line density (line.nz > 0) one more
+// workgroup, index nx, reduces the line histograms.
 template <typename T, bool FROM_PARTIALS>
 __global__ void __launch_bounds__(kRowThreads)
     k_rows_fwd(DepositTarget dep, int nblocks, const int64_t *__restrict__ q, double scale,
                int nx, int ny, int my, int log2my, const cx<T> *__restrict__ tw,
-               cx<T> *__restrict__ at, bool pipe)
+               cx<T> *__restrict__ at, bool pipe, LineSpec line)
 {
+    if (line.nz > 0 && (int)blockIdx.x == nx) {
+        line_table_body<kRowThreads>(line, nblocks);
+        return;
+    }
     rows_fwd_body<T, FROM_PARTIALS, kRowThreads>(dep, nblocks, q, scale, nx, ny, my, log2my, tw,
                                                  at, (int)blockIdx.x, pipe);
 }
@@ -310,12 +363,16 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
 
 // Column l of the row spectra: forward FFT along x, times the Green's
 // spectrum, then the two differentiated inverse transforms, one per wave.
+// The second is the column-inverse of the potential's spectrum before the
+// y difference; bp, when not null, receives it as well (for the node
+// potential).
 template <typename T>
 __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, int ny, int mx,
                                           int log2mx, const cx<T> *__restrict__ tw,
                                           const T *__restrict__ ghat_t, const T *__restrict__ sx,
                                           const T *__restrict__ sy, cx<T> *__restrict__ bx,
-                                          cx<T> *__restrict__ by, int l, bool pipe)
+                                          cx<T> *__restrict__ by, int l, bool pipe,
+                                          cx<T> *__restrict__ bp = nullptr)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
@@ -373,6 +430,8 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     } else {
         for (int i = lane; i < nx; i += 64)
             by[(size_t)i * (ny + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
+        if (bp)
+            for (int i = lane; i < nx; i += 64) bp[(size_t)i * (ny + 1) + l] = conj(res[i]);
     }
 }
 
@@ -380,9 +439,10 @@ template <typename T>
 __global__ void __launch_bounds__(kColThreads)
     k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
            const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
-           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by, bool pipe)
+           const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by, bool pipe,
+           cx<T> *__restrict__ bp)
 {
-    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x, pipe);
+    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x, pipe, bp);
 }
 
 template <typename T>
@@ -397,12 +457,16 @@ __global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
 // i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
+// With bp (the potential's column-inverse spectrum), a second inverse FFT of
+// its Hermitian row writes the node potential phi.
 template <typename T>
 __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
                                               const cx<T> *__restrict__ by, int nx, int ny, int my,
                                               int log2my, const cx<T> *__restrict__ tw,
                                               T *__restrict__ ex, T *__restrict__ ey,
-                                              cx<T> *__restrict__ ef, int i)
+                                              cx<T> *__restrict__ ef, int i,
+                                              const cx<T> *__restrict__ bp = nullptr,
+                                              T *__restrict__ phi = nullptr)
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
@@ -450,15 +514,27 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
             ey[(size_t)i * ny + j] = z.im;
         }
     }
+    if (bp) {
+        cx<T> *a2 = b + my;
+        cx<T> *b2 = a2 + my;
+        const cx<T> *rp = bp + (size_t)i * (ny + 1);
+        for (int l = tid; l <= ny; l += kInvThreads) {
+            const cx<T> P = rp[l];
+            a2[l] = conj(P);
+            if (l > 0 && l < ny) a2[my - l] = P;
+        }
+        const cx<T> *r2 = fft_lds(a2, b2, my, log2my, twl, 1, tid, kInvThreads);
+        for (int j = tid; j < ny; j += kInvThreads) phi[(size_t)i * ny + j] = r2[j].re;
+    }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kInvThreads)
     k_rows_inv(const cx<T> *__restrict__ bx, const cx<T> *__restrict__ by, int nx, int ny, int my,
                int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
-               cx<T> *__restrict__ ef)
+               cx<T> *__restrict__ ef, const cx<T> *__restrict__ bp, T *__restrict__ phi)
 {
-    rows_inv_body<T>(bx, by, nx, ny, my, log2my, tw, ex, ey, ef, (int)blockIdx.x);
+    rows_inv_body<T>(bx, by, nx, ny, my, log2my, tw, ex, ey, ef, (int)blockIdx.x, bp, phi);
 }
 
 template <typename T>
@@ -473,17 +549,20 @@ __global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
 template <typename T>
 hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *ey, void *ef)
 {
+    const bool want_phi = w.line.nz > 0;
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)w.mx;
-    const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)w.my;
+    const size_t inv_lds = (want_phi ? 5 : 3) * sizeof(cx<T>) * (size_t)w.my;
+    cx<T> *bp = want_phi ? (cx<T> *)w.spec_p : nullptr;
     hipLaunchKernelGGL(k_cols<T>, dim3(w.ny + 1), dim3(kColThreads), col_lds, s,
                        (const cx<T> *)w.spec_a, w.nx, w.ny, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
                        (const T *)w.ghat_t, (const T *)w.sx, (const T *)w.sy, (cx<T> *)w.spec_bx,
-                       (cx<T> *)w.spec_by, w.pipe);
+                       (cx<T> *)w.spec_by, w.pipe, bp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kInvThreads), inv_lds, s,
                        (const cx<T> *)w.spec_bx, (const cx<T> *)w.spec_by, w.nx, w.ny, w.my,
-                       w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef);
+                       w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef,
+                       (const cx<T> *)bp, want_phi ? (T *)w.phi : (T *)nullptr);
     return hipGetLastError();
 }
 
@@ -492,11 +571,14 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
                           int nblocks, const int64_t *q, double scale, void *ex, void *ey,
                           void *ef)
 {
-    const size_t row_lds = rows_fwd_hdr_offset<T>(w.ny, w.my) +
-                           (FROM_PARTIALS ? sizeof(BlockHeader) * (size_t)std::max(nblocks, 1) : 0);
-    hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx), dim3(kRowThreads), row_lds, s,
-                       dep, nblocks, q, scale, w.nx, w.ny, w.my, w.log2_my,
-                       (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a, w.pipe);
+    // the line tables come from the partials of a depositing pass only
+    LineSpec line = FROM_PARTIALS ? w.line : LineSpec{};
+    size_t row_lds = rows_fwd_hdr_offset<T>(w.ny, w.my) +
+                     (FROM_PARTIALS ? sizeof(BlockHeader) * (size_t)std::max(nblocks, 1) : 0);
+    if (line.nz > 0) row_lds = std::max(row_lds, sizeof(unsigned long long) * (size_t)kRowThreads);
+    hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx + (line.nz > 0 ? 1 : 0)),
+                       dim3(kRowThreads), row_lds, s, dep, nblocks, q, scale, w.nx, w.ny, w.my,
+                       w.log2_my, (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a, w.pipe, line);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tail<T>(s, w, ex, ey, ef);

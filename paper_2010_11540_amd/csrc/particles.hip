@@ -72,6 +72,37 @@ __device__ __forceinline__ void gather_nodes(const V *e, int l00, int row, const
     fy = (w00 * e00.y + w10 * e10.y + w01 * e01.y + w11 * e11.y) * (TE)(1.0 / kChargeOne);
 }
 
+// Potential at the particle from its four nodes, as gather_nodes.
+template <typename TE>
+__device__ __forceinline__ TE gather_scalar(const TE *u, int l00, int row, const Cic &c)
+{
+    const TE w00 = (TE)c.w00, w10 = (TE)c.w10, w01 = (TE)c.w01, w11 = (TE)c.w11;
+    return (w00 * u[l00] + w10 * u[l00 + row] + w01 * u[l00 + 1] + w11 * u[l00 + row + 1]) *
+           (TE)(1.0 / kChargeOne);
+}
+
+// Node k of the line and the particle's two fixed-point line weights
+// (4096 - a at k, a at k + 1): t = (sigma - z_min)(1/dz), k = floor(t),
+// a = floor((t - k) 4096 + 0.5), the one-dimensional form of cic().  False
+// outside [0, nz - 1) in node units (or NaN).
+struct LineCic {
+    int k;
+    uint32_t w0, w1;
+};
+
+__device__ __forceinline__ bool line_cic(const LineSpec &L, double sg, LineCic &c)
+{
+    const double t = (sg - L.z_min) * L.inv_dz;
+    const bool in = t >= 0.0 && t < (double)(L.nz - 1);
+    const double st = in ? t : 0.0;
+    const double fk = floor(st);
+    const uint32_t a = (uint32_t)(int)floor((st - fk) * 4096.0 + 0.5);
+    c.k = (int)fk;
+    c.w0 = kFracOne - a;
+    c.w1 = a;
+    return in;
+}
+
 // One element applied to one particle (Sec. III): v <- M v for the linear
 // maps, evaluated row by row left to right; the thin sextupole is the kick
 // step of the split thick-sextupole integrator (Sec. III-C).
@@ -373,19 +404,35 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // node the kick gathers from, is staged in LDS beside the tile when it fits.
 // At the end each workgroup writes the bounding box of its tile cells to its
 // slice of the partials (no global atomics).
-// SIX: the particles carry sigma and p_sigma and els may hold thick
-// elements; sigma is loaded and stored with the transverse coordinates.
+// MODE 0: four-dimensional.  MODE 1: the particles carry sigma and p_sigma
+// and els may hold thick elements; sigma is loaded and stored with the
+// transverse coordinates.  MODE 2: as 1, with the long-bunch line density
+// (Sec. IV): the kick is scaled by lambda/lambda_peak at the particle's sigma
+// and p_sigma takes the longitudinal kick -gamma0 kappa phi lambda'/lambda_peak
+// (both tables and the node potential phi from the last solve, interpolated
+// with the particle's line and transverse weights); the deposit adds the
+// particle's two line weights (the one-dimensional form of the charge
+// assignment) to an LDS histogram flushed to the workgroup's row of
+// line.partial.  A particle outside the line is lost like one outside the grid.
 // The body is shared by the single-beam kernel and the batched one: bid is
 // the workgroup's index among the nblk workgroups working on beam P (its
 // slice of the partials and its header), T = nblk * blockDim.x.
-template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+template <typename TE, bool KICK, bool DEPOSIT, int MODE>
 __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom &g,
                                           const TE *__restrict__ ef, double kappa,
                                           const PassElements &els, const DepositTarget &dep,
-                                          unsigned lds_bytes, int bid, int nblk)
+                                          unsigned lds_bytes, int bid, int nblk,
+                                          const LineSpec &line)
 {
     using V = typename Vec2<TE>::type;
-    extern __shared__ __align__(16) unsigned char lds[];
+    constexpr bool SIX = MODE >= 1;
+    constexpr bool LINE = MODE == 2;
+    extern __shared__ __align__(16) unsigned char lds_all[];
+    // LDS: [line histogram (MODE 2)][charge tile][staged field box]
+    const unsigned line_bytes = LINE ? ((unsigned)line.nz * 8u + 15u) & ~15u : 0u;
+    unsigned long long *lh = reinterpret_cast<unsigned long long *>(lds_all);
+    unsigned char *const lds = lds_all + line_bytes;
+    lds_bytes -= line_bytes;
     __shared__ int s_box[4];
     __shared__ int s_count;
     const int64_t T = (int64_t)nblk * blockDim.x;
@@ -464,6 +511,8 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         const int n4 = tile.h * tile.w / 4;  // tile.w is a multiple of 4
         uint4 *q4 = reinterpret_cast<uint4 *>(lq);
         for (int t = threadIdx.x; t < n4; t += blockDim.x) q4[t] = make_uint4(0, 0, 0, 0);
+        if constexpr (LINE)
+            for (int t = threadIdx.x; t < line.nz; t += blockDim.x) lh[t] = 0ull;
         if (threadIdx.x == 0) {
             s_box[0] = INT_MAX;
             s_box[1] = -1;
@@ -496,15 +545,29 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         bool act = lf == 0;
         if (KICK && act) {
             Cic c;
-            if (cic(g, x, y, c)) {
+            LineCic lc;
+            const bool in = cic(g, x, y, c) && (!LINE || line_cic(line, sg, lc));
+            if (in) {
                 TE fx, fy;
                 if (staged && ebox.holds_cell(c.i, c.j))
                     gather_nodes(le, ebox.at(c.i, c.j), ebox.w, c, fx, fy);
                 else
                     gather_nodes(reinterpret_cast<const V *>(ef), c.i * g.ny + c.j, g.ny, c, fx, fy);
-                const double k = kappa * (double)wp;
-                px = px + k * (double)fx;
-                py = py + k * (double)fy;
+                if constexpr (LINE) {
+                    const double w0 = (double)lc.w0, w1 = (double)lc.w1;
+                    const double wl = (w0 * line.lw[lc.k] + w1 * line.lw[lc.k + 1]) / 4096.0;
+                    const double dl = (w0 * line.ld[lc.k] + w1 * line.ld[lc.k + 1]) / 4096.0;
+                    const TE fp = gather_scalar(reinterpret_cast<const TE *>(line.phi),
+                                                c.i * g.ny + c.j, g.ny, c);
+                    const double k = kappa * wl;
+                    px = px + k * (double)fx;
+                    py = py + k * (double)fy;
+                    psg = psg - line.gamma0 * kappa * (double)fp * dl;
+                } else {
+                    const double k = kappa * (double)wp;
+                    px = px + k * (double)fx;
+                    py = py + k * (double)fy;
+                }
             } else if (P.lost) {
                 P.lost[p] = 1;
                 act = false;
@@ -525,10 +588,16 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                 P.y[p] = y;
                 P.py[p] = py;
                 if constexpr (SIX) P.sigma[p] = sg;
+                if constexpr (LINE && KICK) P.psigma[p] = psg;
             }
             if constexpr (DEPOSIT) {
                 Cic c;
-                if (cic(g, x, y, c)) {
+                LineCic lc;
+                if (cic(g, x, y, c) && (!LINE || line_cic(line, sg, lc))) {
+                    if constexpr (LINE) {
+                        atomicAdd(&lh[lc.k], (unsigned long long)lc.w0);
+                        atomicAdd(&lh[lc.k + 1], (unsigned long long)lc.w1);
+                    }
                     if (tile.holds_cell(c.i, c.j)) {
                         // A 32-bit tile cell wraps after 2^32 units (256
                         // particles on one node); the atomic's old value
@@ -590,6 +659,9 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             atomicAdd(&s_count, cnt);
         }
         __syncthreads();
+        if constexpr (LINE)
+            for (int t = threadIdx.x; t < line.nz; t += blockDim.x)
+                line.partial[(size_t)bid * line.nz + t] = lh[t];
         const int i0 = s_box[0], i1 = s_box[1], j0 = s_box[2], j1 = s_box[3];
         if (i0 <= i1) {
             const int c0 = j0 >> 2, nch = (j1 >> 2) - c0 + 1;
@@ -621,8 +693,18 @@ __global__ void __launch_bounds__(1024)
     k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
            PassElements els, DepositTarget dep, unsigned lds_bytes)
 {
-    pass_body<TE, KICK, DEPOSIT, SIX>(P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x,
-                                      (int)gridDim.x);
+    pass_body<TE, KICK, DEPOSIT, SIX ? 1 : 0>(P, g, ef, kappa, els, dep, lds_bytes,
+                                              (int)blockIdx.x, (int)gridDim.x, LineSpec{});
+}
+
+// The pass of a long bunch with its line density (six-dimensional).
+template <typename TE, bool KICK, bool DEPOSIT>
+__global__ void __launch_bounds__(1024)
+    k_pass_line(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
+                PassElements els, DepositTarget dep, unsigned lds_bytes, LineSpec line)
+{
+    pass_body<TE, KICK, DEPOSIT, 2>(P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x,
+                                    (int)gridDim.x, line);
 }
 
 // One pass over every beam of a batch: workgroup -> beam from the batch's
@@ -645,9 +727,10 @@ __global__ void __launch_bounds__(1024)
     P.w = all.w ? all.w + I.p0 : nullptr;
     P.lost = all.lost ? all.lost + I.p0 : nullptr;
     P.n = I.n;
-    pass_body<TE, KICK, DEPOSIT, SIX>(P, I.g, (const TE *)I.ef, steps[k].kappa, steps[k].els,
-                                      I.dep, lds_bytes, (int)blockIdx.x - I.pass_block0,
-                                      I.pass_blocks);
+    pass_body<TE, KICK, DEPOSIT, SIX ? 1 : 0>(P, I.g, (const TE *)I.ef, steps[k].kappa,
+                                              steps[k].els, I.dep, lds_bytes,
+                                              (int)blockIdx.x - I.pass_block0, I.pass_blocks,
+                                              LineSpec{});
 }
 
 // Between two node arrays (ex, ey) and the internal interleaved layout ef
@@ -681,6 +764,17 @@ hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g
     return hipGetLastError();
 }
 
+template <typename TE, bool KICK, bool DEPOSIT>
+hipError_t launch_pass_line_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g,
+                              const void *ef, double kappa, const PassElements &els,
+                              const DepositTarget &dep, int blocks, int threads,
+                              const LineSpec &line)
+{
+    hipLaunchKernelGGL((k_pass_line<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), g_lds_limit,
+                       s, p, g, (const TE *)ef, kappa, els, dep, (unsigned)g_lds_limit, line);
+    return hipGetLastError();
+}
+
 template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
 hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                  const BatchStep *steps, int blocks, int threads)
@@ -700,6 +794,11 @@ void pass_kernels_of(std::vector<const void *> &out)
     out.push_back((const void *)k_pass_batched<TE, true, true, SIX>);
     out.push_back((const void *)k_pass_batched<TE, false, true, SIX>);
     out.push_back((const void *)k_pass_batched<TE, true, false, SIX>);
+    if (SIX) {
+        out.push_back((const void *)k_pass_line<TE, true, true>);
+        out.push_back((const void *)k_pass_line<TE, false, true>);
+        out.push_back((const void *)k_pass_line<TE, true, false>);
+    }
 }
 
 }  // namespace
@@ -749,9 +848,21 @@ hipError_t prepare_pass_kernels(size_t lds_limit)
 
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
-                       bool deposit, const DepositTarget &dep, int blocks, int threads)
+                       bool deposit, const DepositTarget &dep, int blocks, int threads,
+                       const LineSpec *line)
 {
     if (blocks <= 0) return hipSuccess;
+    if (line && (kick || deposit)) {
+#define SCPIC_LL(T)                                                                             \
+    (kick ? (deposit ? launch_pass_line_t<T, true, true>(s, p, g, ef, kappa, els, dep, blocks,  \
+                                                         threads, *line)                        \
+                     : launch_pass_line_t<T, true, false>(s, p, g, ef, kappa, els, dep, blocks, \
+                                                          threads, *line))                      \
+          : launch_pass_line_t<T, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads,   \
+                                               *line))
+        return mixed ? SCPIC_LL(float) : SCPIC_LL(double);
+#undef SCPIC_LL
+    }
     const bool six = has_thick(els);
 #define SCPIC_L(T, K, D, S) launch_pass_t<T, K, D, S>(s, p, g, ef, kappa, els, dep, blocks, threads)
     SCPIC_DISPATCH(SCPIC_L);

@@ -80,6 +80,10 @@ struct scpic_ctx {
     SolveWorkspace sw{};
     void *ef = nullptr;  // internal field, interleaved (Ex, Ey) per node
 
+    // long-bunch line density (scpic_set_line_density); line.nz = 0: off
+    LineSpec line{};
+    std::vector<void *> line_mem;
+
     std::vector<void *> allocations;
     std::vector<GraphEntry> graphs;
     uint64_t use_counter = 0;
@@ -100,8 +104,19 @@ scpic_status dev_alloc(scpic_ctx *c, void **p, size_t bytes)
     return SCPIC_OK;
 }
 
+void free_line(scpic_ctx *c)
+{
+    for (void *p : c->line_mem) hipFree(p);
+    c->line_mem.clear();
+    c->line = LineSpec{};
+    c->sw.line = LineSpec{};
+    c->sw.spec_p = nullptr;
+    c->sw.phi = nullptr;
+}
+
 void free_all(scpic_ctx *c)
 {
+    free_line(c);
     for (auto &g : c->graphs)
         if (g.exec) hipGraphExecDestroy(g.exec);
     c->graphs.clear();
@@ -247,12 +262,28 @@ void emit_segment(std::vector<PassOp> &ops, bool kick, double kappa,
     } while (at < n);
 }
 
+// The line density, when on, goes with every pass that kicks or deposits.
+scpic_status check_line(const scpic_ctx *c, const scpic_particles *p)
+{
+    if (c->line.nz == 0) return SCPIC_OK;
+    if (!c->sw.pipe)
+        return fail(SCPIC_EUNSUPPORTED, "the line density needs the grounded pipe solver (its "
+                                        "longitudinal kick uses the absolute potential)");
+    if (p->n > 0 && (!p->sigma || !p->psigma))
+        return fail(SCPIC_EINVAL, "the line density needs the particles' sigma and psigma");
+    if (p->w)
+        return fail(SCPIC_EINVAL, "per-particle kick weights and the line density exclude each "
+                                  "other (the line density computes the weights)");
+    return SCPIC_OK;
+}
+
 scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
                           const PassOp &op)
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
+    const LineSpec *line = c->line.nz > 0 && (op.kick || op.deposit) ? &c->line : nullptr;
     hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
-                               op.els, op.deposit, c->dep, blocks, c->pass_threads);
+                               op.els, op.deposit, c->dep, blocks, c->pass_threads, line);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
     if (op.deposit) c->last_deposit_blocks = blocks;
     return SCPIC_OK;
@@ -710,6 +741,8 @@ scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t ki
     for (auto *e : els)
         if (e->kind == SCPIC_EL_SC) return fail(SCPIC_EINVAL, "a pass takes no SC element");
     if (scpic_status st = check_longitudinal(els, parts)) return st;
+    if (kick || deposit)
+        if (scpic_status st = check_line(ctx, parts)) return st;
     PassOp op;
     op.kick = kick != 0;
     op.kappa = kappa;
@@ -736,6 +769,77 @@ scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey)
     return SCPIC_OK;
 }
 
+scpic_status scpic_set_line_density(scpic_ctx *ctx, int32_t nz, double z_min, double dz,
+                                    double gamma0)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (nz != 0 && (nz < 8 || nz > kMaxLineNodes))
+        return fail(SCPIC_EINVAL, "nz must be 0 or in [8, " + std::to_string(kMaxLineNodes) + "]");
+    if (nz != 0 && !(dz > 0.0 && std::isfinite(dz) && std::isfinite(z_min) &&
+                     std::isfinite(gamma0) && gamma0 >= 1.0))
+        return fail(SCPIC_EINVAL, "dz must be positive and finite, z_min finite, gamma0 >= 1");
+    // captured turns carry the line: drop them once queued work is done
+    SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (auto &g : ctx->graphs)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    ctx->graphs.clear();
+    free_line(ctx);
+    if (nz == 0) return SCPIC_OK;
+    const size_t cells = (size_t)ctx->grid.nx * ctx->grid.ny;
+    const size_t es = field_elem_size(ctx);
+    const size_t sizes[4] = {sizeof(unsigned long long) * (size_t)ctx->max_blocks * nz,
+                             sizeof(double) * 2 * (size_t)nz, es * cells,
+                             2 * es * (size_t)ctx->grid.nx * (ctx->grid.ny + 1)};
+    void *mem[4] = {};
+    for (int k = 0; k < 4; ++k) {
+        hipError_t e = hipMalloc(&mem[k], sizes[k]);
+        if (e != hipSuccess) {
+            for (int j = 0; j < k; ++j) hipFree(mem[j]);
+            return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+    }
+    for (int k = 0; k < 4; ++k) ctx->line_mem.push_back(mem[k]);
+    // a kick before the first deposit sees an empty line (no kick)
+    SCPIC_HIP_TRY(hipMemset(mem[1], 0, sizes[1]), "hipMemset");
+    SCPIC_HIP_TRY(hipMemset(mem[2], 0, sizes[2]), "hipMemset");
+    LineSpec &L = ctx->line;
+    L.nz = nz;
+    L.z_min = z_min;
+    L.dz = dz;
+    L.inv_dz = 1.0 / dz;
+    L.gamma0 = gamma0;
+    L.partial = (unsigned long long *)mem[0];
+    L.lw = (double *)mem[1];
+    L.ld = L.lw + nz;
+    L.phi = mem[2];
+    ctx->sw.line = L;
+    ctx->sw.phi = mem[2];
+    ctx->sw.spec_p = mem[3];
+    return SCPIC_OK;
+}
+
+scpic_status scpic_get_line_state(scpic_ctx *ctx, void *phi, double *lw, double *ld)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (ctx->line.nz == 0) return fail(SCPIC_EINVAL, "the line density is off");
+    const size_t cells = (size_t)ctx->grid.nx * ctx->grid.ny;
+    if (phi)
+        SCPIC_HIP_TRY(hipMemcpyAsync(phi, ctx->line.phi, field_elem_size(ctx) * cells,
+                                     hipMemcpyDeviceToDevice, ctx->stream),
+                      "hipMemcpyAsync");
+    if (lw)
+        SCPIC_HIP_TRY(hipMemcpyAsync(lw, ctx->line.lw, sizeof(double) * ctx->line.nz,
+                                     hipMemcpyDeviceToDevice, ctx->stream),
+                      "hipMemcpyAsync");
+    if (ld)
+        SCPIC_HIP_TRY(hipMemcpyAsync(ld, ctx->line.ld, sizeof(double) * ctx->line.nz,
+                                     hipMemcpyDeviceToDevice, ctx->stream),
+                      "hipMemcpyAsync");
+    return SCPIC_OK;
+}
+
 scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scpic_element *turn,
                          int32_t n_el, int32_t n_turns)
 {
@@ -746,6 +850,11 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
     std::vector<const scpic_element *> all;
     if (scpic_status st = collect_elements(turn, n_el, all, true)) return st;
     if (scpic_status st = check_longitudinal(all, parts)) return st;
+    for (const scpic_element *e : all)
+        if (e->kind == SCPIC_EL_SC) {
+            if (scpic_status st = check_line(ctx, parts)) return st;
+            break;
+        }
     if (n_turns == 0 || all.empty() || parts->n == 0) return SCPIC_OK;
     const double scale = 1.0 / (kChargeOne * (double)parts->n);
 

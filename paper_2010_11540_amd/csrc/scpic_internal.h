@@ -68,11 +68,26 @@ struct DepositTarget {
 struct ParticlePtrs {
     double *x, *px, *y, *py;
     double *sigma;         // longitudinal pair, may be null (four-dimensional)
-    const double *psigma;
+    double *psigma;
     const float *w;  // per-particle kick weight (2.5D line density), may be null
     uint8_t *lost;
     int64_t n;
 };
+
+// Line density of a long bunch (Sec. IV) as a pass sees it: the line of nz
+// nodes z_min + k dz, the node tables of the last solve (lambda/lambda_peak
+// and lambda'/lambda_peak) and its node potential for the kick, and the
+// per-workgroup histograms [max_blocks][nz] a depositing pass writes.
+struct LineSpec {
+    int32_t nz;
+    double z_min, inv_dz, dz, gamma0;
+    double *lw, *ld;                 // [nz], written by the grid phase
+    const void *phi;                 // [nx*ny] node potential, double or float
+    unsigned long long *partial;     // [max_blocks][nz]
+};
+
+// Most nodes of a line-density grid.
+constexpr int kMaxLineNodes = 512;
 
 // One beam of a batch, as the batched kernels see it: its particles (a
 // contiguous range of the concatenated arrays), its grid, its partials and
@@ -109,9 +124,12 @@ struct BatchLaunch {
 
 // ---- launchers (particles.hip) ------------------------------------------
 // ef: interleaved node field (Ex, Ey per node), double or float per mixed.
+// line: the long-bunch line density (kick scaled by lambda/lambda_peak, the
+// longitudinal kick, the line histogram with the deposit), or null.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
-                       bool deposit, const DepositTarget &dep, int blocks, int threads);
+                       bool deposit, const DepositTarget &dep, int blocks, int threads,
+                       const LineSpec *line = nullptr);
 
 // Copy (ex, ey) into the interleaved field ef, or back.
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
@@ -144,6 +162,12 @@ struct SolveWorkspace {
     void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [ny+1] sin(2 pi l / my)/dy
     void *spec_a;        // [ny+1][nx] complex, rows transformed
     void *spec_bx, *spec_by;  // [nx][ny+1] complex, after the column pass
+    // line density (nz > 0): the potential's column-inverse spectrum
+    // [nx][ny+1] complex, the node potential [nx*ny], and the line tables
+    // reduced from the pass's histograms
+    void *spec_p = nullptr;
+    void *phi = nullptr;
+    LineSpec line{};
 };
 
 // Field of charge grid q: to separate arrays ex, ey (ef == nullptr) or

@@ -343,6 +343,12 @@ def workload(name: str, n: int | None = None, seed: int | None = None) -> dict:
         lat = ring(4.2, 4.3, 200, kc / 200)
         return {"name": name, "parts": long_bunch_kv(n, seed, a, b), "grid": grid, "lattice": lat,
                 "turns": 1000, "n": n, "seed": seed}
+    elif name in ("line", "line_small"):
+        # the thick rings with the long-bunch line density: 128 nodes over
+        # +-6 sigma_z (sigma_z = 1 m), grounded-pipe solver
+        w = workload("thick" if name == "line" else "thick_small", n, seed)
+        w.update(name=name, line=make_line(6.0, 128), solver="pipe")
+        return w
     elif name in ("thick", "thick_small"):
         # 6D beam through thick chromatic quadrupoles and SABA2 thick
         # sextupoles: 1 mm rms at the kick in both planes, p_sigma rms 1e-3

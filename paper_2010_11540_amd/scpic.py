@@ -32,7 +32,7 @@ EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_track", "scpic_set_option", "scpic_pass", "scpic_reduce_solve",
            "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
            "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_autotune",
-           "scpic_batch_get_field")
+           "scpic_batch_get_field", "scpic_set_line_density", "scpic_get_line_state")
 
 
 class Grid(ctypes.Structure):
@@ -79,6 +79,8 @@ def load_library(path: Path | str | None = None):
     L.scpic_pass.argtypes = [vp, ctypes.POINTER(Particles), i32, dbl, vp, i32, i32]
     L.scpic_reduce_solve.argtypes = [vp, dbl]
     L.scpic_get_field.argtypes = [vp, vp, vp]
+    L.scpic_set_line_density.argtypes = [vp, i32, dbl, dbl, dbl]
+    L.scpic_get_line_state.argtypes = [vp, vp, vp, vp]
     L.scpic_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid),
                                      ctypes.POINTER(i64), i32, i32, vp]
     L.scpic_batch_destroy.argtypes = [vp]
@@ -275,6 +277,31 @@ class Context:
         ey = torch.empty_like(ex)
         _check(self._lib.scpic_get_field(self._h, ex.data_ptr(), ey.data_ptr()))
         return ex, ey
+
+    def set_line_density(self, line: dict | None, stream=None):
+        """Turn the long-bunch line density on (line = {"nz", "z_min", "dz",
+        "gamma0"}) or off (None)."""
+        self._sync_stream(stream)
+        if line is None:
+            _check(self._lib.scpic_set_line_density(self._h, 0, 0.0, 1.0, 1.0))
+            self.line_nz = 0
+        else:
+            _check(self._lib.scpic_set_line_density(self._h, int(line["nz"]), float(line["z_min"]),
+                                                    float(line["dz"]), float(line["gamma0"])))
+            self.line_nz = int(line["nz"])
+
+    def get_line_state(self, stream=None):
+        """(phi, lw, ld) of the last solve: node potential (nx*ny) and the
+        line tables lambda/lambda_peak, lambda'/lambda_peak (nz each)."""
+        self._sync_stream(stream)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        phi = torch.empty(self.ncell, dtype=self.field_dtype, device=dev)
+        nz = getattr(self, "line_nz", 0)
+        lw = torch.empty(max(nz, 1), dtype=torch.float64, device=dev)
+        ld = torch.empty_like(lw)
+        _check(self._lib.scpic_get_line_state(self._h, phi.data_ptr(), lw.data_ptr(),
+                                              ld.data_ptr()))
+        return phi, lw[:nz], ld[:nz]
 
 
 def _grid_struct(grid: dict) -> Grid:
