@@ -298,7 +298,16 @@ __device__ __forceinline__ void line_table_body(const LineSpec &L, int nblocks)
     const int k = tid % nz, g = tid / nz;
     unsigned long long s = 0;
     if (g < groups)
-        for (int b = g; b < nblocks; b += groups) s += L.partial[(size_t)b * nz + k];
+        for (int b0 = g; b0 < nblocks; b0 += 8 * groups) {
+            unsigned long long v[8];  // eight loads in flight per round
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u * groups;
+                v[u] = b < nblocks ? L.partial[(size_t)b * nz + k] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
     acc[tid] = s;
     __syncthreads();
     unsigned long long h = 0;

@@ -428,9 +428,11 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     constexpr bool SIX = MODE >= 1;
     constexpr bool LINE = MODE == 2;
     extern __shared__ __align__(16) unsigned char lds_all[];
-    // LDS: [line histogram (MODE 2)][charge tile][staged field box]
-    const unsigned line_bytes = LINE ? ((unsigned)line.nz * 8u + 15u) & ~15u : 0u;
-    unsigned long long *lh = reinterpret_cast<unsigned long long *>(lds_all);
+    // LDS: [line histogram (MODE 2)][charge tile][staged field box].  The
+    // histogram counts in 32 bits: a workgroup adds 4096 per particle and the
+    // host launches no workgroup with more than 2^20 particles.
+    const unsigned line_bytes = LINE ? ((unsigned)line.nz * 4u + 15u) & ~15u : 0u;
+    uint32_t *lh = reinterpret_cast<uint32_t *>(lds_all);
     unsigned char *const lds = lds_all + line_bytes;
     lds_bytes -= line_bytes;
     __shared__ int s_box[4];
@@ -512,7 +514,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         uint4 *q4 = reinterpret_cast<uint4 *>(lq);
         for (int t = threadIdx.x; t < n4; t += blockDim.x) q4[t] = make_uint4(0, 0, 0, 0);
         if constexpr (LINE)
-            for (int t = threadIdx.x; t < line.nz; t += blockDim.x) lh[t] = 0ull;
+            for (int t = threadIdx.x; t < line.nz; t += blockDim.x) lh[t] = 0u;
         if (threadIdx.x == 0) {
             s_box[0] = INT_MAX;
             s_box[1] = -1;
@@ -595,8 +597,8 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                 LineCic lc;
                 if (cic(g, x, y, c) && (!LINE || line_cic(line, sg, lc))) {
                     if constexpr (LINE) {
-                        atomicAdd(&lh[lc.k], (unsigned long long)lc.w0);
-                        atomicAdd(&lh[lc.k + 1], (unsigned long long)lc.w1);
+                        atomicAdd(&lh[lc.k], lc.w0);
+                        atomicAdd(&lh[lc.k + 1], lc.w1);
                     }
                     if (tile.holds_cell(c.i, c.j)) {
                         // A 32-bit tile cell wraps after 2^32 units (256
@@ -661,7 +663,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         __syncthreads();
         if constexpr (LINE)
             for (int t = threadIdx.x; t < line.nz; t += blockDim.x)
-                line.partial[(size_t)bid * line.nz + t] = lh[t];
+                line.partial[(size_t)bid * line.nz + t] = (unsigned long long)lh[t];
         const int i0 = s_box[0], i1 = s_box[1], j0 = s_box[2], j1 = s_box[3];
         if (i0 <= i1) {
             const int c0 = j0 >> 2, nch = (j1 >> 2) - c0 + 1;

@@ -274,6 +274,11 @@ scpic_status check_line(const scpic_ctx *c, const scpic_particles *p)
     if (p->w)
         return fail(SCPIC_EINVAL, "per-particle kick weights and the line density exclude each "
                                   "other (the line density computes the weights)");
+    // the per-workgroup line histogram counts 4096 per particle in 32 bits
+    const int blocks = blocks_for(c, p->n, true);
+    if (blocks > 0 && (p->n + blocks - 1) / blocks > (int64_t)(1 << 20) - 1024)
+        return fail(SCPIC_EUNSUPPORTED, "the line density takes at most 2^20 particles per "
+                                        "workgroup (raise SCPIC_OPT_PASS_BLOCKS)");
     return SCPIC_OK;
 }
 
