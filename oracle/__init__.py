@@ -22,7 +22,11 @@ What each function follows (arXiv:2010.11540):
               direct sum over charged nodes; or the grounded rectangular pipe
               of Sec. IV-B (5-point Laplacian, u = 0 on the walls), written out
               as its discrete sine-eigenvector expansion.
-  field       E = -grad(u) (Sec. IV-C), by centred differences on the nodes.
+  field       E = -grad(u) (Sec. IV-C), by centred differences on the nodes;
+              or (gather="bspline") the analytic gradient of the bicubic
+              surface through the 4x4 nodes around the particle's cell (the
+              interpolation of Sec. IV-C read as the uniform cubic B-spline
+              with the node potentials as control points).
   kick        Sec. IV: transverse kick proportional to the field at the
               particle times the distance since the previous kick, and (2.5D
               form) to the line density at the particle relative to its peak.
@@ -95,6 +99,17 @@ def lib():
         L.orc_track.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
                                 i32, vp, vp, i32, i32]
         L.orc_track.restype = i32
+        L.orc_bspline_eval.argtypes = [i64, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp]
+        L.orc_bspline_eval.restype = None
+        L.orc_kick_bspline.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl,
+                                       vp, dbl]
+        L.orc_kick_bspline.restype = None
+        L.orc_space_charge_bspline.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl,
+                                               dbl, dbl, dbl, dbl, i32]
+        L.orc_space_charge_bspline.restype = i64
+        L.orc_track_gather.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl,
+                                       dbl, i32, vp, vp, i32, i32, i32]
+        L.orc_track_gather.restype = i32
         L.orc_deposit_line.argtypes = [i64, vp, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, i32, dbl,
                                        dbl, vp, vp]
         L.orc_deposit_line.restype = i64
@@ -218,8 +233,31 @@ def kick(parts: dict, grid, ex: np.ndarray, ey: np.ndarray, kappa: float) -> Non
                    _ptr(ey), float(kappa))
 
 
-def space_charge(parts: dict, grid, scale: float, kappa: float, solver: str = "open"):
-    """One full space-charge step in place; returns (ex, ey, n_in)."""
+def bspline_eval(x: np.ndarray, y: np.ndarray, phi: np.ndarray, grid):
+    """(u, ex, ey) of the B-spline surface of the node potential phi (as
+    potential() returns it) at the points; NaN outside the domain."""
+    x, y = _f64(x), _f64(y)
+    phi = _f64(phi).ravel()
+    n = x.shape[0]
+    u, ex, ey = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_bspline_eval(n, _ptr(x), _ptr(y), _ptr(phi), *_grid_args(grid), _ptr(u), _ptr(ex),
+                           _ptr(ey))
+    return u, ex, ey
+
+
+def space_charge(parts: dict, grid, scale: float, kappa: float, solver: str = "open",
+                 gather: str = "cic"):
+    """One full space-charge step in place; returns (ex, ey, n_in) (the node
+    field; with gather="bspline" the kick takes the B-spline gradient instead
+    and (None, None, n_in) is returned)."""
+    if gather == "bspline":
+        n = parts["x"].shape[0]
+        n_in = lib().orc_space_charge_bspline(n, _ptr(parts["x"]), _ptr(parts["px"]),
+                                              _ptr(parts["y"]), _ptr(parts["py"]),
+                                              _ptr(parts.get("lost")), _ptr(_weights(parts)),
+                                              *_grid_args(grid), float(scale), float(kappa),
+                                              _pipe(solver))
+        return None, None, int(n_in)
     nx, ny = int(grid["nx"]), int(grid["ny"])
     ex = np.zeros(nx * ny)
     ey = np.zeros(nx * ny)
@@ -235,14 +273,16 @@ def _pipe(solver: str) -> int:
     return {"open": 0, "pipe": 1}[solver]
 
 
-def track(parts: dict, grid, elements, n_turns: int, solver: str = "open") -> None:
+def track(parts: dict, grid, elements, n_turns: int, solver: str = "open",
+          gather: str = "cic") -> None:
     """In place: n_turns through the one-turn element sequence."""
     kind, par = _elements(elements)
     n = parts["x"].shape[0]
-    rc = lib().orc_track(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
-                         _ptr(parts["py"]), *_longitudinal(parts), _ptr(parts.get("lost")),
-                         _ptr(_weights(parts)), *_grid_args(grid), len(kind), _ptr(kind),
-                         _ptr(par), int(n_turns), _pipe(solver))
+    rc = lib().orc_track_gather(n, _ptr(parts["x"]), _ptr(parts["px"]), _ptr(parts["y"]),
+                                _ptr(parts["py"]), *_longitudinal(parts), _ptr(parts.get("lost")),
+                                _ptr(_weights(parts)), *_grid_args(grid), len(kind), _ptr(kind),
+                                _ptr(par), int(n_turns), _pipe(solver),
+                                {"cic": 0, "bspline": 1}[gather])
     if rc != 0:
         raise ValueError("thick elements need sigma and psigma, and n >= 1 sextupole steps")
 

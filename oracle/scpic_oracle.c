@@ -494,14 +494,124 @@ void orc_kick(int64_t n, const double *x, double *px, const double *y, double *p
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Potential interpolation (Sec. IV-C): the bicubic surface through the 4x4  */
+/* nodes around the particle's cell, field as its analytic gradient.         */
+/* ------------------------------------------------------------------------ */
+
+/* Uniform cubic B-spline basis on the cell fraction t in [0, 1): the weights
+ * of nodes i-1, i, i+1, i+2 and their derivatives in t. */
+static void bspline3(double t, double b[4], double db[4])
+{
+    double u = 1.0 - t;
+    b[0] = u * u * u / 6.0;
+    b[1] = (3.0 * t * t * t - 6.0 * t * t + 4.0) / 6.0;
+    b[2] = (-3.0 * t * t * t + 3.0 * t * t + 3.0 * t + 1.0) / 6.0;
+    b[3] = t * t * t / 6.0;
+    db[0] = -u * u / 2.0;
+    db[1] = (3.0 * t * t - 4.0 * t) / 2.0;
+    db[2] = (-3.0 * t * t + 2.0 * t + 1.0) / 2.0;
+    db[3] = t * t / 2.0;
+}
+
+/* Potential and field at (x, y) from the node potential phi ((nx+2)(ny+2),
+ * nodes -1..nx by -1..ny as orc_potential writes it):
+ *   u = sum_{m,n} phi[i+m-1][j+n-1] B_m(tx) B_n(ty),  E = -grad u,
+ * with i = floor(tx), tx = (x - x_min)/dx (and likewise in y).  Returns 0
+ * outside the half-open domain of the charge assignment. */
+static int bspline_field(const orc_grid *g, const double *phi, double x, double y, double *u,
+                         double *ex, double *ey)
+{
+    double tx = (x - g->x_min) * g->inv_dx;
+    double ty = (y - g->y_min) * g->inv_dy;
+    if (!(tx >= 0.0 && tx < (double)(g->nx - 1))) return 0;
+    if (!(ty >= 0.0 && ty < (double)(g->ny - 1))) return 0;
+    int i = (int)floor(tx), j = (int)floor(ty);
+    double bx[4], dbx[4], by[4], dby[4];
+    bspline3(tx - i, bx, dbx);
+    bspline3(ty - j, by, dby);
+    int64_t s = g->ny + 2;
+    double su = 0.0, sx = 0.0, sy = 0.0;
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) {
+            /* node (i+m-1, j+n-1) sits at row i+m, column j+n of phi */
+            double v = phi[(int64_t)(i + m) * s + (j + n)];
+            su += v * bx[m] * by[n];
+            sx += v * dbx[m] * by[n];
+            sy += v * bx[m] * dby[n];
+        }
+    *u = su;
+    *ex = -sx * g->inv_dx;
+    *ey = -sy * g->inv_dy;
+    return 1;
+}
+
+/* Evaluate the interpolated potential and field at n points (for the pins);
+ * points outside the domain get NaN. */
+void orc_bspline_eval(int64_t n, const double *x, const double *y, const double *phi, int nx,
+                      int ny, double x_min, double y_min, double dx, double dy, double *u,
+                      double *ex, double *ey)
+{
+    orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+    for (int64_t p = 0; p < n; ++p)
+        if (!bspline_field(&g, phi, x[p], y[p], &u[p], &ex[p], &ey[p])) u[p] = ex[p] = ey[p] = NAN;
+}
+
+/* Kick with the interpolated field: p += kappa w_p E(x, y), E from the
+ * B-spline surface of the node potential. */
+void orc_kick_bspline(int64_t n, const double *x, double *px, const double *y, double *py,
+                      uint8_t *lost, const float *wt, int nx, int ny, double x_min, double y_min,
+                      double dx, double dy, const double *phi, double kappa)
+{
+    orc_grid g = make_grid(nx, ny, x_min, y_min, dx, dy);
+    int64_t p;
+#pragma omp parallel for schedule(static)
+    for (p = 0; p < n; ++p) {
+        if (lost && lost[p]) continue;
+        double u, ex, ey;
+        if (!bspline_field(&g, phi, x[p], y[p], &u, &ex, &ey)) {
+            if (lost) lost[p] = 1;
+            continue;
+        }
+        double k = wt ? kappa * (double)wt[p] : kappa;
+        px[p] += k * ex;
+        py[p] += k * ey;
+    }
+}
+
 /* The whole space-charge step at one location: deposit, potential (open
  * boundary, or the grounded pipe when pipe != 0), field, kick.  scale converts charge units to the normalised density (1/(2^24 N0)
  * for N0 initial macro-particles, so the total charge is 1).  ex/ey, when not
  * NULL, receive the node field.  Returns the number of particles deposited. */
+static int64_t space_charge_step(int64_t n, double *x, double *px, double *y, double *py,
+                                 uint8_t *lost, const float *wt, int nx, int ny, double x_min,
+                                 double y_min, double dx, double dy, double scale, double kappa,
+                                 double *ex_out, double *ey_out, int pipe, int bspline);
+
 int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py, uint8_t *lost,
                          const float *wt, int nx, int ny, double x_min, double y_min, double dx,
                          double dy, double scale, double kappa, double *ex_out, double *ey_out,
                          int pipe)
+{
+    return space_charge_step(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale, kappa,
+                             ex_out, ey_out, pipe, 0);
+}
+
+/* As orc_space_charge, with the kick's field from the B-spline surface of the
+ * potential (Sec. IV-C) instead of the cloud-in-cell gather of node fields. */
+int64_t orc_space_charge_bspline(int64_t n, double *x, double *px, double *y, double *py,
+                                 uint8_t *lost, const float *wt, int nx, int ny, double x_min,
+                                 double y_min, double dx, double dy, double scale, double kappa,
+                                 int pipe)
+{
+    return space_charge_step(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale, kappa,
+                             NULL, NULL, pipe, 1);
+}
+
+static int64_t space_charge_step(int64_t n, double *x, double *px, double *y, double *py,
+                                 uint8_t *lost, const float *wt, int nx, int ny, double x_min,
+                                 double y_min, double dx, double dy, double scale, double kappa,
+                                 double *ex_out, double *ey_out, int pipe, int bspline)
 {
     int64_t cells = (int64_t)nx * ny;
     int64_t *q = (int64_t *)malloc(sizeof(int64_t) * (size_t)cells);
@@ -514,7 +624,10 @@ int64_t orc_space_charge(int64_t n, double *x, double *px, double *y, double *py
     else
         orc_potential(q, scale, nx, ny, dx, dy, phi);
     orc_field(phi, nx, ny, dx, dy, ex, ey);
-    orc_kick(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
+    if (bspline)
+        orc_kick_bspline(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, phi, kappa);
+    else
+        orc_kick(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, ex, ey, kappa);
     if (!ex_out) free(ex);
     if (!ey_out) free(ey);
     free(phi);
@@ -706,10 +819,26 @@ int orc_track_line(int64_t n, double *x, double *px, double *y, double *py, doub
  * its own kappa.  The charge scale is 1/(2^24 n): n is the initial particle
  * count, so lost particles take their charge with them.  Returns -1 (nothing
  * tracked) under the conditions orc_push rejects. */
+int orc_track_gather(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
+                     double *psigma, uint8_t *lost, const float *wt, int nx, int ny,
+                     double x_min, double y_min, double dx, double dy, int n_el,
+                     const int32_t *kind, const double *par, int n_turns, int pipe, int bspline);
+
 int orc_track(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
               double *psigma, uint8_t *lost, const float *wt, int nx, int ny, double x_min,
               double y_min, double dx, double dy, int n_el, const int32_t *kind,
               const double *par, int n_turns, int pipe)
+{
+    return orc_track_gather(n, x, px, y, py, sigma, psigma, lost, wt, nx, ny, x_min, y_min, dx,
+                            dy, n_el, kind, par, n_turns, pipe, 0);
+}
+
+/* As orc_track; bspline != 0 takes every kick's field from the B-spline
+ * surface of the potential (Sec. IV-C). */
+int orc_track_gather(int64_t n, double *x, double *px, double *y, double *py, double *sigma,
+                     double *psigma, uint8_t *lost, const float *wt, int nx, int ny,
+                     double x_min, double y_min, double dx, double dy, int n_el,
+                     const int32_t *kind, const double *par, int n_turns, int pipe, int bspline)
 {
     double scale = 1.0 / (ORC_CHARGE_ONE * (double)n);
     for (int e = 0; e < n_el; ++e) {
@@ -719,8 +848,8 @@ int orc_track(int64_t n, double *x, double *px, double *y, double *py, double *s
     for (int t = 0; t < n_turns; ++t)
         for (int e = 0; e < n_el; ++e) {
             if (kind[e] == ORC_SC)
-                orc_space_charge(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale,
-                                 par[16 * e], NULL, NULL, pipe);
+                space_charge_step(n, x, px, y, py, lost, wt, nx, ny, x_min, y_min, dx, dy, scale,
+                                  par[16 * e], NULL, NULL, pipe, bspline);
             else
                 orc_push(n, x, px, y, py, sigma, psigma, lost, 1, kind + e, par + 16 * e);
         }
