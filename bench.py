@@ -75,6 +75,9 @@ def parse():
                     help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
                          "bunch with line-density kick weights, 256^2; batch: 64-beam tune scan")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--gather", default="cic", choices=["cic", "bspline"],
+                    help="kick field: cloud-in-cell gather of the node field, or the gradient of "
+                         "the bicubic B-spline surface of the node potential")
     ap.add_argument("--solver", default="open", choices=["open", "pipe"],
                     help="open-boundary convolution, or the grounded rectangular pipe")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
@@ -318,6 +321,8 @@ def main():
         ctx.set_option(scpic.OPT_SOLVER, scpic.SOLVER_PIPE)
     if "line" in w:
         ctx.set_line_density(w["line"])
+    if args.gather == "bspline":
+        ctx.set_option(scpic.OPT_GATHER, scpic.GATHER_BSPLINE)
     if args.no_graph:
         ctx.set_option(scpic.OPT_USE_GRAPH, 0)
     if args.pass_threads:
@@ -386,7 +391,7 @@ def main():
            "line": "FODO cell of thick elements, line density"}.get(args.workload, "2x2 map")
     roofline = {
         "bound": "hbm",
-        "kernel": (f"k_pass{'_line' if line_on else ''}<"
+        "kernel": (f"k_pass{'_line' if line_on else ('_bspline' if args.gather == 'bspline' else '')}<"
                    f"{'double' if args.precision == 'fp64' else 'float'},kick,deposit"
                    f"{',six' if six and not line_on else ''}> (gather+kick, {seg}, CIC deposit, "
                    "flush)"),
@@ -394,7 +399,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(n) if args.workload == "production" else None,
+        "traffic": (measured_traffic(n) if args.workload == "production" and args.gather == "cic"
+                    else None),
         "algorithmic_bytes_per_launch": unit_bytes * n,
         "avg_launch_us": round(pass_us, 3),
         "grid_phase_us": round(grid_us, 3),
@@ -437,6 +443,7 @@ def main():
             "sc_steps_per_turn": steps_per_turn,
             "precision": args.precision,
             "solver": args.solver,
+            "gather": args.gather,
             "graph": not args.no_graph,
             "alive_after": alive,
             "gpu_event_ms": round(gpu_ms, 3),

@@ -224,6 +224,23 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
  *                            Applies to scpic_solve, scpic_track and
  *                            scpic_reduce_solve; waits for the context's
  *                            stream and drops its cached turn graphs.
+ *   SCPIC_OPT_GATHER         SCPIC_GATHER_CIC (default): the kick gathers the
+ *                            node field with the deposit's four weights;
+ *                            SCPIC_GATHER_BSPLINE: the interpolation of
+ *                            Sec. IV-C, read as the uniform bicubic B-spline
+ *                            with the node potentials as control points --
+ *                            phi(x, y) = sum_{m,n=0..3} u[i+m-1][j+n-1]
+ *                            B_m(tx) B_n(ty) over the 4x4 nodes around the
+ *                            particle's cell (tx, ty its exact cell
+ *                            fractions, B the uniform cubic basis) -- and the
+ *                            kick takes E = -grad phi analytically.  The
+ *                            solve then also keeps the potential on nodes
+ *                            -1..nx by -1..ny (scpic_get_potential).  Applies
+ *                            to scpic_track and scpic_pass (scpic_kick gathers
+ *                            the field it is given); not with the line
+ *                            density.  Allocates the potential's buffers on
+ *                            first use, waits for the stream and drops the
+ *                            cached turn graphs.
  * Results do not depend on the launch shape. */
 #define SCPIC_OPT_USE_GRAPH 1
 #define SCPIC_OPT_PASS_BLOCKS 2
@@ -231,6 +248,9 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
 #define SCPIC_OPT_SOLVER 4
 #define SCPIC_SOLVER_OPEN 0
 #define SCPIC_SOLVER_PIPE 1
+#define SCPIC_OPT_GATHER 5
+#define SCPIC_GATHER_CIC 0
+#define SCPIC_GATHER_BSPLINE 1
 scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value);
 
 /* Fused particle pass, one launch: optionally kick with the context's
@@ -268,20 +288,26 @@ scpic_status scpic_get_field(scpic_ctx *ctx, void *ex, void *ey);
  * the transverse one (carried by kappa).  phi is the potential of the grounded
  * pipe: the line density needs SCPIC_SOLVER_PIPE (SCPIC_EUNSUPPORTED at track
  * time otherwise), the particles' sigma and psigma, and no per-particle
- * weights w (SCPIC_EINVAL).  A particle whose sigma leaves [z_min,
+ * weights w (SCPIC_EINVAL), and the cloud-in-cell gather (SCPIC_EUNSUPPORTED
+ * with SCPIC_GATHER_BSPLINE).  A particle whose sigma leaves [z_min,
  * z_min + (nz-1) dz) is lost like one leaving the grid.
  * nz in [8, 512], dz > 0, gamma0 >= 1, all finite.  This call synchronises the
  * context's stream and allocates the line's buffers (the histograms of up to
- * the context's largest workgroup count, the node tables, the node potential
- * and one spectrum); tracking allocates nothing. */
+ * the context's largest workgroup count and the node tables; the node
+ * potential and its spectrum once); tracking allocates nothing. */
 scpic_status scpic_set_line_density(scpic_ctx *ctx, int32_t nz, double z_min, double dz,
                                     double gamma0);
 
-/* Copy the line state of the last solve: the node potential phi (device,
- * nx*ny, double or float per precision, row-major) and the node tables lw, ld
- * (device, nz doubles each); any pointer may be NULL.  SCPIC_EINVAL when the
- * line density is off. */
-scpic_status scpic_get_line_state(scpic_ctx *ctx, void *phi, double *lw, double *ld);
+/* Copy the line tables of the last solve, lw and ld (device, nz doubles
+ * each; either may be NULL).  SCPIC_EINVAL when the line density is off. */
+scpic_status scpic_get_line_state(scpic_ctx *ctx, double *lw, double *ld);
+
+/* Copy the node potential of the last solve (device, (nx+2)*(ny+2) doubles or
+ * floats per precision, row-major: node (i, j) for i = -1..nx, j = -1..ny at
+ * [(i+1)*(ny+2) + j+1]), the potential whose centred differences are the
+ * field.  Kept while the line density or the B-spline gather is on
+ * (SCPIC_EINVAL otherwise). */
+scpic_status scpic_get_potential(scpic_ctx *ctx, void *phi);
 
 /* ---- batches of independent beams --------------------------------------
  * Many independent beams (a tune scan, Sec. V; beams of different sizes on

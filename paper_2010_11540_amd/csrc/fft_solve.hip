@@ -373,8 +373,10 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
 // Column l of the row spectra: forward FFT along x, times the Green's
 // spectrum, then the two differentiated inverse transforms, one per wave.
 // The second is the column-inverse of the potential's spectrum before the
-// y difference; bp, when not null, receives it as well (for the node
-// potential).
+// y difference; bp, when not null, receives it as well for the node
+// potential, on rows -1..nx (row i at bp[(i + 1) * (ny + 1)]; row -1 is the
+// periodic row mx - 1, which the zero padding or the odd extension makes the
+// potential's value one node outside the grid).
 template <typename T>
 __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, int ny, int mx,
                                           int log2mx, const cx<T> *__restrict__ tw,
@@ -440,7 +442,8 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
         for (int i = lane; i < nx; i += 64)
             by[(size_t)i * (ny + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
         if (bp)
-            for (int i = lane; i < nx; i += 64) bp[(size_t)i * (ny + 1) + l] = conj(res[i]);
+            for (int i = lane - 1; i <= nx; i += 64)
+                bp[(size_t)(i + 1) * (ny + 1) + l] = conj(res[i < 0 ? mx - 1 : i]);
     }
 }
 
@@ -467,7 +470,9 @@ __global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
 // i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
 // With bp (the potential's column-inverse spectrum), a second inverse FFT of
-// its Hermitian row writes the node potential phi.
+// its Hermitian row writes row i of the node potential phi on columns
+// -1..ny (phi[(i + 1) * (ny + 2) + j + 1]); rows -1 and nx (i < 0 or
+// i == nx) write only that.
 template <typename T>
 __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
                                               const cx<T> *__restrict__ by, int nx, int ny, int my,
@@ -482,8 +487,10 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
     cx<T> *a = twl + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
-    const cx<T> *rx = bx + (size_t)i * (ny + 1);
-    const cx<T> *ry = by + (size_t)i * (ny + 1);
+    // rows -1 and nx have no field: their (unused) spectrum loads read row 0
+    const int fi = (i >= 0 && i < nx) ? i : 0;
+    const cx<T> *rx = bx + (size_t)fi * (ny + 1);
+    const cx<T> *ry = by + (size_t)fi * (ny + 1);
     constexpr int kPerT = kMaxFft / kInvThreads;          // twiddles per thread
     constexpr int kPerL = kMaxFft / 2 / kInvThreads + 1;  // spectrum entries per thread
     cx<T> vt[kPerT], vx[kPerL], vy[kPerL];
@@ -513,27 +520,31 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
             if (l > 0 && l < ny) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
         }
     }
-    const cx<T> *r = fft_lds(a, b, my, log2my, twl, 1, tid, kInvThreads);
-    if (ef) {
-        for (int j = tid; j < ny; j += kInvThreads) ef[(size_t)i * ny + j] = conj(r[j]);
-    } else {
-        for (int j = tid; j < ny; j += kInvThreads) {
-            const cx<T> z = conj(r[j]);
-            ex[(size_t)i * ny + j] = z.re;
-            ey[(size_t)i * ny + j] = z.im;
+    const bool field_row = i >= 0 && i < nx;
+    if (field_row) {
+        const cx<T> *r = fft_lds(a, b, my, log2my, twl, 1, tid, kInvThreads);
+        if (ef) {
+            for (int j = tid; j < ny; j += kInvThreads) ef[(size_t)i * ny + j] = conj(r[j]);
+        } else {
+            for (int j = tid; j < ny; j += kInvThreads) {
+                const cx<T> z = conj(r[j]);
+                ex[(size_t)i * ny + j] = z.re;
+                ey[(size_t)i * ny + j] = z.im;
+            }
         }
     }
     if (bp) {
         cx<T> *a2 = b + my;
         cx<T> *b2 = a2 + my;
-        const cx<T> *rp = bp + (size_t)i * (ny + 1);
+        const cx<T> *rp = bp + (size_t)(i + 1) * (ny + 1);
         for (int l = tid; l <= ny; l += kInvThreads) {
             const cx<T> P = rp[l];
             a2[l] = conj(P);
             if (l > 0 && l < ny) a2[my - l] = P;
         }
         const cx<T> *r2 = fft_lds(a2, b2, my, log2my, twl, 1, tid, kInvThreads);
-        for (int j = tid; j < ny; j += kInvThreads) phi[(size_t)i * ny + j] = r2[j].re;
+        T *row = phi + (size_t)(i + 1) * (ny + 2);
+        for (int j = tid - 1; j <= ny; j += kInvThreads) row[j + 1] = r2[j < 0 ? my - 1 : j].re;
     }
 }
 
@@ -543,7 +554,10 @@ __global__ void __launch_bounds__(kInvThreads)
                int log2my, const cx<T> *__restrict__ tw, T *__restrict__ ex, T *__restrict__ ey,
                cx<T> *__restrict__ ef, const cx<T> *__restrict__ bp, T *__restrict__ phi)
 {
-    rows_inv_body<T>(bx, by, nx, ny, my, log2my, tw, ex, ey, ef, (int)blockIdx.x, bp, phi);
+    // workgroups nx and nx + 1 (launched with the potential) take rows -1 and nx
+    const int r = (int)blockIdx.x;
+    const int i = r < nx ? r : (r == nx ? -1 : nx);
+    rows_inv_body<T>(bx, by, nx, ny, my, log2my, tw, ex, ey, ef, i, bp, phi);
 }
 
 template <typename T>
@@ -558,7 +572,7 @@ __global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
 template <typename T>
 hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *ey, void *ef)
 {
-    const bool want_phi = w.line.nz > 0;
+    const bool want_phi = w.want_phi;
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)w.mx;
     const size_t inv_lds = (want_phi ? 5 : 3) * sizeof(cx<T>) * (size_t)w.my;
     cx<T> *bp = want_phi ? (cx<T> *)w.spec_p : nullptr;
@@ -568,7 +582,7 @@ hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *e
                        (cx<T> *)w.spec_by, w.pipe, bp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx), dim3(kInvThreads), inv_lds, s,
+    hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx + (want_phi ? 2 : 0)), dim3(kInvThreads), inv_lds, s,
                        (const cx<T> *)w.spec_bx, (const cx<T> *)w.spec_by, w.nx, w.ny, w.my,
                        w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef,
                        (const cx<T> *)bp, want_phi ? (T *)w.phi : (T *)nullptr);

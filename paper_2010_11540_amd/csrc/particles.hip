@@ -81,6 +81,50 @@ __device__ __forceinline__ TE gather_scalar(const TE *u, int l00, int row, const
            (TE)(1.0 / kChargeOne);
 }
 
+// Field at (x, y) in cell c (c.i, c.j from cic()) from the bicubic B-spline
+// surface of the node potential u (nodes -1..nx by -1..ny, row length ny + 2):
+//   phi = sum_{m,n} u[i+m-1][j+n-1] B_m(tx) B_n(ty),  E = -grad phi,
+// with the uniform cubic basis B_m on the exact cell fractions (not the
+// 12-bit ones of the deposit); rows are contracted first.
+template <typename TE>
+__device__ __forceinline__ void bspline_field(const GridGeom &g, const TE *__restrict__ u,
+                                              double x, double y, const Cic &c, TE &fx, TE &fy)
+{
+    const TE tx = (TE)((x - g.x_min) * g.inv_dx - (double)c.i);
+    const TE ty = (TE)((y - g.y_min) * g.inv_dy - (double)c.j);
+    TE bx[4], dbx[4], by[4], dby[4];
+    auto basis = [](TE t, TE *b, TE *db) {
+        const TE v = TE(1) - t, t2 = t * t;
+        b[0] = v * v * v * TE(1.0 / 6.0);
+        b[1] = (TE(3) * t2 * t - TE(6) * t2 + TE(4)) * TE(1.0 / 6.0);
+        b[2] = (TE(-3) * t2 * t + TE(3) * t2 + TE(3) * t + TE(1)) * TE(1.0 / 6.0);
+        b[3] = t2 * t * TE(1.0 / 6.0);
+        db[0] = -v * v * TE(0.5);
+        db[1] = (TE(3) * t2 - TE(4) * t) * TE(0.5);
+        db[2] = (TE(-3) * t2 + TE(2) * t + TE(1)) * TE(0.5);
+        db[3] = t2 * TE(0.5);
+    };
+    basis(tx, bx, dbx);
+    basis(ty, by, dby);
+    const int row = g.ny + 2;
+    const TE *base = u + (size_t)c.i * row + c.j;  // node (i-1, j-1)
+    TE v[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) v[m][n] = base[m * row + n];
+    TE sx = 0, sy = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const TE r = v[m][0] * by[0] + v[m][1] * by[1] + v[m][2] * by[2] + v[m][3] * by[3];
+        const TE d = v[m][0] * dby[0] + v[m][1] * dby[1] + v[m][2] * dby[2] + v[m][3] * dby[3];
+        sx = sx + dbx[m] * r;
+        sy = sy + bx[m] * d;
+    }
+    fx = -sx * (TE)g.inv_dx;
+    fy = -sy * (TE)g.inv_dy;
+}
+
 // Node k of the line and the particle's two fixed-point line weights
 // (4096 - a at k, a at k + 1): t = (sigma - z_min)(1/dz), k = floor(t),
 // a = floor((t - k) 4096 + 0.5), the one-dimensional form of cic().  False
@@ -404,9 +448,12 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // node the kick gathers from, is staged in LDS beside the tile when it fits.
 // At the end each workgroup writes the bounding box of its tile cells to its
 // slice of the partials (no global atomics).
-// MODE 0: four-dimensional.  MODE 1: the particles carry sigma and p_sigma
-// and els may hold thick elements; sigma is loaded and stored with the
-// transverse coordinates.  MODE 2: as 1, with the long-bunch line density
+// MODE is a set of flags.  0: four-dimensional.  1: the particles carry sigma
+// and p_sigma and els may hold thick elements; sigma is loaded and stored with
+// the transverse coordinates.  4: the kick's field is the analytic gradient of
+// the bicubic B-spline surface of the node potential (Sec. IV-C), ef then
+// pointing at the potential on nodes -1..nx by -1..ny.  2: six-dimensional,
+// with the long-bunch line density
 // (Sec. IV): the kick is scaled by lambda/lambda_peak at the particle's sigma
 // and p_sigma takes the longitudinal kick -gamma0 kappa phi lambda'/lambda_peak
 // (both tables and the node potential phi from the last solve, interpolated
@@ -425,8 +472,9 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                                           const LineSpec &line)
 {
     using V = typename Vec2<TE>::type;
-    constexpr bool SIX = MODE >= 1;
-    constexpr bool LINE = MODE == 2;
+    constexpr bool LINE = (MODE & 2) != 0;
+    constexpr bool SIX = (MODE & 1) != 0 || LINE;
+    constexpr bool BSPL = (MODE & 4) != 0;
     extern __shared__ __align__(16) unsigned char lds_all[];
     // LDS: [line histogram (MODE 2)][charge tile][staged field box].  The
     // histogram counts in 32 bits: a workgroup adds 4096 per particle and the
@@ -484,7 +532,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         const bool known = hd.i0 >= 0 && hd.i0 <= hd.i1 && hd.j0 >= 0 && hd.j0 <= hd.j1 &&
                            hd.i1 < g.nx && hd.j1 < g.ny;
         ebox = Box{hd.i0, hd.j0, hd.i1 - hd.i0 + 1, hd.j1 - hd.j0 + 1};
-        staged = !whole && known &&
+        staged = !BSPL && !whole && known &&
                  ((size_t)ebox.h * ebox.w + 2) * sizeof(V) + tile_bytes <= (size_t)lds_bytes;
         if (staged) {
             // four nodes per thread per round; indices past the box repeat
@@ -551,7 +599,9 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             const bool in = cic(g, x, y, c) && (!LINE || line_cic(line, sg, lc));
             if (in) {
                 TE fx, fy;
-                if (staged && ebox.holds_cell(c.i, c.j))
+                if constexpr (BSPL)
+                    bspline_field(g, ef, x, y, c, fx, fy);
+                else if (staged && ebox.holds_cell(c.i, c.j))
                     gather_nodes(le, ebox.at(c.i, c.j), ebox.w, c, fx, fy);
                 else
                     gather_nodes(reinterpret_cast<const V *>(ef), c.i * g.ny + c.j, g.ny, c, fx, fy);
@@ -560,7 +610,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                     const double wl = (w0 * line.lw[lc.k] + w1 * line.lw[lc.k + 1]) / 4096.0;
                     const double dl = (w0 * line.ld[lc.k] + w1 * line.ld[lc.k + 1]) / 4096.0;
                     const TE fp = gather_scalar(reinterpret_cast<const TE *>(line.phi),
-                                                c.i * g.ny + c.j, g.ny, c);
+                                                (c.i + 1) * (g.ny + 2) + c.j + 1, g.ny + 2, c);
                     const double k = kappa * wl;
                     px = px + k * (double)fx;
                     py = py + k * (double)fy;
@@ -699,6 +749,17 @@ __global__ void __launch_bounds__(1024)
                                               (int)blockIdx.x, (int)gridDim.x, LineSpec{});
 }
 
+// The pass with the B-spline field (phi: the node potential on nodes -1..nx
+// by -1..ny).
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+__global__ void __launch_bounds__(1024)
+    k_pass_bspline(ParticlePtrs P, GridGeom g, const TE *__restrict__ phi, double kappa,
+                   PassElements els, DepositTarget dep, unsigned lds_bytes)
+{
+    pass_body<TE, KICK, DEPOSIT, 4 | (SIX ? 1 : 0)>(P, g, phi, kappa, els, dep, lds_bytes,
+                                                    (int)blockIdx.x, (int)gridDim.x, LineSpec{});
+}
+
 // The pass of a long bunch with its line density (six-dimensional).
 template <typename TE, bool KICK, bool DEPOSIT>
 __global__ void __launch_bounds__(1024)
@@ -766,6 +827,17 @@ hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g
     return hipGetLastError();
 }
 
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+hipError_t launch_pass_bspline_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g,
+                                 const void *phi, double kappa, const PassElements &els,
+                                 const DepositTarget &dep, int blocks, int threads)
+{
+    const size_t lds = DEPOSIT ? g_lds_limit : 0;
+    hipLaunchKernelGGL((k_pass_bspline<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds,
+                       s, p, g, (const TE *)phi, kappa, els, dep, (unsigned)lds);
+    return hipGetLastError();
+}
+
 template <typename TE, bool KICK, bool DEPOSIT>
 hipError_t launch_pass_line_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g,
                               const void *ef, double kappa, const PassElements &els,
@@ -796,6 +868,7 @@ void pass_kernels_of(std::vector<const void *> &out)
     out.push_back((const void *)k_pass_batched<TE, true, true, SIX>);
     out.push_back((const void *)k_pass_batched<TE, false, true, SIX>);
     out.push_back((const void *)k_pass_batched<TE, true, false, SIX>);
+    out.push_back((const void *)k_pass_bspline<TE, true, true, SIX>);
     if (SIX) {
         out.push_back((const void *)k_pass_line<TE, true, true>);
         out.push_back((const void *)k_pass_line<TE, false, true>);
@@ -851,9 +924,20 @@ hipError_t prepare_pass_kernels(size_t lds_limit)
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
                        bool deposit, const DepositTarget &dep, int blocks, int threads,
-                       const LineSpec *line)
+                       const LineSpec *line, const void *bspline_phi)
 {
     if (blocks <= 0) return hipSuccess;
+    if (bspline_phi && kick) {
+        const bool six = has_thick(els);
+#define SCPIC_LB(T, D, S) \
+    launch_pass_bspline_t<T, true, D, S>(s, p, g, bspline_phi, kappa, els, dep, blocks, threads)
+        if (mixed)
+            return six ? (deposit ? SCPIC_LB(float, true, true) : SCPIC_LB(float, false, true))
+                       : (deposit ? SCPIC_LB(float, true, false) : SCPIC_LB(float, false, false));
+        return six ? (deposit ? SCPIC_LB(double, true, true) : SCPIC_LB(double, false, true))
+                   : (deposit ? SCPIC_LB(double, true, false) : SCPIC_LB(double, false, false));
+#undef SCPIC_LB
+    }
     if (line && (kick || deposit)) {
 #define SCPIC_LL(T)                                                                             \
     (kick ? (deposit ? launch_pass_line_t<T, true, true>(s, p, g, ef, kappa, els, dep, blocks,  \

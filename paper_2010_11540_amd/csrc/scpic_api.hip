@@ -83,6 +83,8 @@ struct scpic_ctx {
     // long-bunch line density (scpic_set_line_density); line.nz = 0: off
     LineSpec line{};
     std::vector<void *> line_mem;
+    // kick field from the B-spline surface of the potential (SCPIC_OPT_GATHER)
+    bool bspline = false;
 
     std::vector<void *> allocations;
     std::vector<GraphEntry> graphs;
@@ -110,8 +112,31 @@ void free_line(scpic_ctx *c)
     c->line_mem.clear();
     c->line = LineSpec{};
     c->sw.line = LineSpec{};
-    c->sw.spec_p = nullptr;
-    c->sw.phi = nullptr;
+    c->sw.want_phi = c->bspline;
+}
+
+// The node potential (nodes -1..nx by -1..ny) and its spectrum, allocated
+// once, when the line density or the B-spline field first needs them.
+scpic_status ensure_potential(scpic_ctx *c)
+{
+    if (c->sw.phi) return SCPIC_OK;
+    const size_t es = field_elem_size(c);
+    void *phi = nullptr, *spec = nullptr;
+    if (scpic_status st = dev_alloc(c, &phi, es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 2)))
+        return st;
+    if (scpic_status st = dev_alloc(c, &spec, 2 * es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 1)))
+        return st;
+    SCPIC_HIP_TRY(hipMemset(phi, 0, es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 2)), "hipMemset");
+    c->sw.phi = phi;
+    c->sw.spec_p = spec;
+    return SCPIC_OK;
+}
+
+void drop_graphs(scpic_ctx *c)
+{
+    for (auto &g : c->graphs)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
 }
 
 void free_all(scpic_ctx *c)
@@ -274,6 +299,8 @@ scpic_status check_line(const scpic_ctx *c, const scpic_particles *p)
     if (p->w)
         return fail(SCPIC_EINVAL, "per-particle kick weights and the line density exclude each "
                                   "other (the line density computes the weights)");
+    if (c->bspline)
+        return fail(SCPIC_EUNSUPPORTED, "the line density takes the cloud-in-cell gather");
     // the per-workgroup line histogram counts 4096 per particle in 32 bits
     const int blocks = blocks_for(c, p->n, true);
     if (blocks > 0 && (p->n + blocks - 1) / blocks > (int64_t)(1 << 20) - 1024)
@@ -287,8 +314,9 @@ scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *pa
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
     const LineSpec *line = c->line.nz > 0 && (op.kick || op.deposit) ? &c->line : nullptr;
+    const void *bphi = c->bspline && op.kick ? c->sw.phi : nullptr;
     hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
-                               op.els, op.deposit, c->dep, blocks, c->pass_threads, line);
+                               op.els, op.deposit, c->dep, blocks, c->pass_threads, line, bphi);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
     if (op.deposit) c->last_deposit_blocks = blocks;
     return SCPIC_OK;
@@ -661,6 +689,19 @@ scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
         ctx->sw.pipe = pipe;
         return ctx->mixed ? upload_tables<float>(ctx) : upload_tables<double>(ctx);
     }
+    case SCPIC_OPT_GATHER: {
+        if (value != SCPIC_GATHER_CIC && value != SCPIC_GATHER_BSPLINE)
+            return fail(SCPIC_EINVAL, "gather must be SCPIC_GATHER_CIC or SCPIC_GATHER_BSPLINE");
+        const bool bs = value == SCPIC_GATHER_BSPLINE;
+        if (bs == ctx->bspline) return SCPIC_OK;
+        SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+        drop_graphs(ctx);
+        if (bs)
+            if (scpic_status st = ensure_potential(ctx)) return st;
+        ctx->bspline = bs;
+        ctx->sw.want_phi = bs || ctx->line.nz > 0;
+        return SCPIC_OK;
+    }
     case SCPIC_OPT_PASS_THREADS:
         if (value != 256 && value != 512 && value != 1024)
             return fail(SCPIC_EINVAL, "pass threads must be 256, 512 or 1024");
@@ -786,28 +827,23 @@ scpic_status scpic_set_line_density(scpic_ctx *ctx, int32_t nz, double z_min, do
         return fail(SCPIC_EINVAL, "dz must be positive and finite, z_min finite, gamma0 >= 1");
     // captured turns carry the line: drop them once queued work is done
     SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    for (auto &g : ctx->graphs)
-        if (g.exec) hipGraphExecDestroy(g.exec);
-    ctx->graphs.clear();
+    drop_graphs(ctx);
     free_line(ctx);
     if (nz == 0) return SCPIC_OK;
-    const size_t cells = (size_t)ctx->grid.nx * ctx->grid.ny;
-    const size_t es = field_elem_size(ctx);
-    const size_t sizes[4] = {sizeof(unsigned long long) * (size_t)ctx->max_blocks * nz,
-                             sizeof(double) * 2 * (size_t)nz, es * cells,
-                             2 * es * (size_t)ctx->grid.nx * (ctx->grid.ny + 1)};
-    void *mem[4] = {};
-    for (int k = 0; k < 4; ++k) {
+    if (scpic_status st = ensure_potential(ctx)) return st;
+    const size_t sizes[2] = {sizeof(unsigned long long) * (size_t)ctx->max_blocks * nz,
+                             sizeof(double) * 2 * (size_t)nz};
+    void *mem[2] = {};
+    for (int k = 0; k < 2; ++k) {
         hipError_t e = hipMalloc(&mem[k], sizes[k]);
         if (e != hipSuccess) {
             for (int j = 0; j < k; ++j) hipFree(mem[j]);
             return fail(SCPIC_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
         }
     }
-    for (int k = 0; k < 4; ++k) ctx->line_mem.push_back(mem[k]);
+    for (int k = 0; k < 2; ++k) ctx->line_mem.push_back(mem[k]);
     // a kick before the first deposit sees an empty line (no kick)
     SCPIC_HIP_TRY(hipMemset(mem[1], 0, sizes[1]), "hipMemset");
-    SCPIC_HIP_TRY(hipMemset(mem[2], 0, sizes[2]), "hipMemset");
     LineSpec &L = ctx->line;
     L.nz = nz;
     L.z_min = z_min;
@@ -817,23 +853,33 @@ scpic_status scpic_set_line_density(scpic_ctx *ctx, int32_t nz, double z_min, do
     L.partial = (unsigned long long *)mem[0];
     L.lw = (double *)mem[1];
     L.ld = L.lw + nz;
-    L.phi = mem[2];
+    L.phi = ctx->sw.phi;
     ctx->sw.line = L;
-    ctx->sw.phi = mem[2];
-    ctx->sw.spec_p = mem[3];
+    ctx->sw.want_phi = true;
     return SCPIC_OK;
 }
 
-scpic_status scpic_get_line_state(scpic_ctx *ctx, void *phi, double *lw, double *ld)
+scpic_status scpic_get_potential(scpic_ctx *ctx, void *phi)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (!phi) return fail(SCPIC_EINVAL, "phi is NULL");
+    if (!ctx->sw.want_phi)
+        return fail(SCPIC_EINVAL, "the potential is kept only with the line density or the "
+                                  "B-spline gather");
+    SCPIC_HIP_TRY(hipMemcpyAsync(phi, ctx->sw.phi,
+                                 field_elem_size(ctx) * (size_t)(ctx->grid.nx + 2) *
+                                     (ctx->grid.ny + 2),
+                                 hipMemcpyDeviceToDevice, ctx->stream),
+                  "hipMemcpyAsync");
+    return SCPIC_OK;
+}
+
+scpic_status scpic_get_line_state(scpic_ctx *ctx, double *lw, double *ld)
 {
     g_last_error.clear();
     if (scpic_status st = check_ctx(ctx)) return st;
     if (ctx->line.nz == 0) return fail(SCPIC_EINVAL, "the line density is off");
-    const size_t cells = (size_t)ctx->grid.nx * ctx->grid.ny;
-    if (phi)
-        SCPIC_HIP_TRY(hipMemcpyAsync(phi, ctx->line.phi, field_elem_size(ctx) * cells,
-                                     hipMemcpyDeviceToDevice, ctx->stream),
-                      "hipMemcpyAsync");
     if (lw)
         SCPIC_HIP_TRY(hipMemcpyAsync(lw, ctx->line.lw, sizeof(double) * ctx->line.nz,
                                      hipMemcpyDeviceToDevice, ctx->stream),

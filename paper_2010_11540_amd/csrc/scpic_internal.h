@@ -82,7 +82,7 @@ struct LineSpec {
     int32_t nz;
     double z_min, inv_dz, dz, gamma0;
     double *lw, *ld;                 // [nz], written by the grid phase
-    const void *phi;                 // [nx*ny] node potential, double or float
+    const void *phi;                 // [(nx+2)*(ny+2)] node potential (nodes -1..n)
     unsigned long long *partial;     // [max_blocks][nz]
 };
 
@@ -126,10 +126,12 @@ struct BatchLaunch {
 // ef: interleaved node field (Ex, Ey per node), double or float per mixed.
 // line: the long-bunch line density (kick scaled by lambda/lambda_peak, the
 // longitudinal kick, the line histogram with the deposit), or null.
+// bspline_phi: the node potential (nodes -1..nx by -1..ny) when the kick takes
+// the B-spline field (Sec. IV-C) instead of gathering ef; not with a line.
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
                        bool deposit, const DepositTarget &dep, int blocks, int threads,
-                       const LineSpec *line = nullptr);
+                       const LineSpec *line = nullptr, const void *bspline_phi = nullptr);
 
 // Copy (ex, ey) into the interleaved field ef, or back.
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
@@ -162,9 +164,11 @@ struct SolveWorkspace {
     void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [ny+1] sin(2 pi l / my)/dy
     void *spec_a;        // [ny+1][nx] complex, rows transformed
     void *spec_bx, *spec_by;  // [nx][ny+1] complex, after the column pass
-    // line density (nz > 0): the potential's column-inverse spectrum
-    // [nx][ny+1] complex, the node potential [nx*ny], and the line tables
-    // reduced from the pass's histograms
+    // node potential (want_phi; for the line density or the B-spline gather):
+    // the potential's column-inverse spectrum [nx+2][ny+1] complex (rows
+    // -1..nx) and the potential on nodes -1..nx by -1..ny [(nx+2)*(ny+2)];
+    // with line.nz > 0 the line tables reduced from the pass's histograms
+    bool want_phi = false;
     void *spec_p = nullptr;
     void *phi = nullptr;
     LineSpec line{};

@@ -23,7 +23,8 @@ _LIB_PATH = Path(__file__).resolve().parent / "libscpic.so"
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, MIXED = 0, 1
-OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS, OPT_SOLVER = 1, 2, 3, 4
+OPT_USE_GRAPH, OPT_PASS_BLOCKS, OPT_PASS_THREADS, OPT_SOLVER, OPT_GATHER = 1, 2, 3, 4, 5
+GATHER_CIC, GATHER_BSPLINE = 0, 1
 SOLVER_OPEN, SOLVER_PIPE = 0, 1
 
 # every function the header declares, for load checks
@@ -32,7 +33,8 @@ EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_track", "scpic_set_option", "scpic_pass", "scpic_reduce_solve",
            "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
            "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_autotune",
-           "scpic_batch_get_field", "scpic_set_line_density", "scpic_get_line_state")
+           "scpic_batch_get_field", "scpic_set_line_density", "scpic_get_line_state",
+           "scpic_get_potential")
 
 
 class Grid(ctypes.Structure):
@@ -80,7 +82,8 @@ def load_library(path: Path | str | None = None):
     L.scpic_reduce_solve.argtypes = [vp, dbl]
     L.scpic_get_field.argtypes = [vp, vp, vp]
     L.scpic_set_line_density.argtypes = [vp, i32, dbl, dbl, dbl]
-    L.scpic_get_line_state.argtypes = [vp, vp, vp, vp]
+    L.scpic_get_line_state.argtypes = [vp, vp, vp]
+    L.scpic_get_potential.argtypes = [vp, vp]
     L.scpic_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Grid),
                                      ctypes.POINTER(i64), i32, i32, vp]
     L.scpic_batch_destroy.argtypes = [vp]
@@ -291,17 +294,25 @@ class Context:
             self.line_nz = int(line["nz"])
 
     def get_line_state(self, stream=None):
-        """(phi, lw, ld) of the last solve: node potential (nx*ny) and the
-        line tables lambda/lambda_peak, lambda'/lambda_peak (nz each)."""
+        """(lw, ld): the line tables lambda/lambda_peak, lambda'/lambda_peak
+        of the last solve (nz each)."""
         self._sync_stream(stream)
         dev = torch.device("cuda", torch.cuda.current_device())
-        phi = torch.empty(self.ncell, dtype=self.field_dtype, device=dev)
         nz = getattr(self, "line_nz", 0)
         lw = torch.empty(max(nz, 1), dtype=torch.float64, device=dev)
         ld = torch.empty_like(lw)
-        _check(self._lib.scpic_get_line_state(self._h, phi.data_ptr(), lw.data_ptr(),
-                                              ld.data_ptr()))
-        return phi, lw[:nz], ld[:nz]
+        _check(self._lib.scpic_get_line_state(self._h, lw.data_ptr(), ld.data_ptr()))
+        return lw[:nz], ld[:nz]
+
+    def get_potential(self, stream=None):
+        """The node potential of the last solve on nodes -1..nx by -1..ny, as
+        an (nx+2, ny+2) tensor."""
+        self._sync_stream(stream)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        nx, ny = self.grid["nx"], self.grid["ny"]
+        phi = torch.empty((nx + 2) * (ny + 2), dtype=self.field_dtype, device=dev)
+        _check(self._lib.scpic_get_potential(self._h, phi.data_ptr()))
+        return phi.reshape(nx + 2, ny + 2)
 
 
 def _grid_struct(grid: dict) -> Grid:

@@ -1,0 +1,178 @@
+"""The B-spline field (the potential interpolation of Sec. IV-C read as the
+uniform bicubic B-spline of the node potentials, field = its analytic
+gradient) on the HIP path, through the C ABI, against the FP64 oracle.
+
+Bars:
+  node potential, nodes -1..n   max|phi - phi_ref| / max|phi_ref| <= 1e-12 (FP64),
+                                1e-5 (FP32)
+  one step / one turn           max|u - u_ref| / rms(u_ref) <= 1e-10 (FP64); the
+                                FP32 potential bar carried through the gradient
+                                for the mixed form (see _mixed_bar)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2010_11540_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+COORDS = ("x", "px", "y", "py")
+
+
+def _say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _dev(parts):
+    from paper_2010_11540_amd.scpic import to_device
+    return to_device(parts)
+
+
+def _host(parts):
+    return {k: v.cpu().numpy() for k, v in parts.items()}
+
+
+def _err(h, ref, coords=COORDS):
+    return max(np.abs(h[k] - ref[k]).max() / max(ref[k].std(), 1e-300) for k in coords)
+
+
+def _ctx(gpu, grid, precision="fp64", solver="open"):
+    ctx = gpu.Context(grid, precision)
+    if solver == "pipe":
+        ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_PIPE)
+    ctx.set_option(gpu.OPT_GATHER, gpu.GATHER_BSPLINE)
+    return ctx
+
+
+def _mixed_bar(phi, grid, kappa, n_kicks, ref):
+    """An FP32 potential within 1e-5 of max|phi| moves the B-spline gradient by
+    at most 1e-5 max|phi| (sum of |B'| over the stencil, <= 2) / spacing per
+    axis; over n_kicks kicks, relative to the rms momenta, times 2."""
+    de = 1e-5 * np.abs(phi).max() * 2.0 / min(grid["dx"], grid["dy"])
+    return 2 * n_kicks * kappa * de / min(ref["px"].std(), ref["py"].std())
+
+
+@pytest.mark.parametrize("solver", ["open", "pipe"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_potential_on_extended_nodes(gpu, orc, solver, precision, tol):
+    _say(f"node potential -1..n, {solver}, {precision}")
+    n = 50_000
+    grid = inputs.make_grid(64, 32, 6e-3, 4e-3)
+    p0 = inputs.gaussian_beam(n, 91, 1e-3, 1e-3, 0.7e-3, 1e-3)
+    q, _ = orc.deposit(inputs.copy_parts(p0), grid)
+    scale = 1.0 / ((1 << 24) * n)
+    phi_ref = orc.potential(q, scale, grid, solver)
+    with _ctx(gpu, grid, precision, solver) as ctx:
+        d = _dev(p0)
+        ctx.track(d, inputs.sc_kick(0.0), 1)
+        phi = ctx.get_potential().double().cpu().numpy()
+    err = np.abs(phi - phi_ref).max() / np.abs(phi_ref).max()
+    print(f"[bspline] potential error {err:.3e}", flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("solver", ["open", "pipe"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bspline_step_matches_oracle(gpu, orc, solver, precision):
+    _say(f"B-spline step {solver} {precision}")
+    n = 40_000
+    grid = inputs.make_grid(64)
+    p0 = inputs.gaussian_beam(n, 92)
+    kappa = 4e-7
+    ref = inputs.copy_parts(p0)
+    orc.space_charge(ref, grid, 1.0 / ((1 << 24) * n), kappa, solver=solver, gather="bspline")
+    with _ctx(gpu, grid, precision, solver) as ctx:
+        d = _dev(p0)
+        ctx.track(d, inputs.sc_kick(kappa), 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _err(h, ref)
+    if precision == "fp64":
+        bar = 1e-10
+    else:
+        q, _ = orc.deposit(inputs.copy_parts(p0), grid)
+        bar = _mixed_bar(orc.potential(q, 1.0 / ((1 << 24) * n), grid, solver), grid, kappa, 1,
+                         ref)
+    print(f"[bspline step] {solver} {precision}: {err:.3e} (bar {bar:.3e})", flush=True)
+    assert err <= bar
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_bspline_small_one_turn_fp64(gpu, orc, use_graph):
+    _say(f"B-spline small workload 1 turn (graph={use_graph})")
+    w = inputs.workload("small")
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, w["grid"], w["lattice"], 1, gather="bspline")
+    with _ctx(gpu, w["grid"]) as ctx:
+        ctx.set_option(gpu.OPT_USE_GRAPH, int(use_graph))
+        d = _dev(w["parts"])
+        ctx.track(d, w["lattice"], 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _err(h, ref)
+    print(f"[bspline small] one-turn error {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_bspline_thick_small_pipe_one_turn_fp64(gpu, orc):
+    _say("B-spline thick_small workload in the pipe, 1 turn")
+    w = inputs.workload("thick_small")
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, w["grid"], w["lattice"], 1, solver="pipe", gather="bspline")
+    with _ctx(gpu, w["grid"], solver="pipe") as ctx:
+        d = _dev(w["parts"])
+        ctx.track(d, w["lattice"], 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _err(h, ref, COORDS + ("sigma",))
+    print(f"[bspline thick pipe] one-turn error {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_bspline_production_full_size_one_step(gpu, orc):
+    _say("B-spline production workload, full size, one step")
+    w = inputs.workload("production")
+    lat = w["lattice"][:2]
+    assert list(lat["kind"]) == [inputs.LIN4X4, inputs.SC]
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, w["grid"], lat, 1, gather="bspline")
+    with _ctx(gpu, w["grid"]) as ctx:
+        d = _dev(w["parts"])
+        ctx.track(d, lat, 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _err(h, ref)
+    print(f"[bspline production] one-step error {err:.3e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_back_to_cic_and_unsupported_combinations(gpu):
+    _say("B-spline option off again == CIC; with the line density: unsupported")
+    w = inputs.workload("small")
+    outs = []
+    for toggle in (False, True):
+        with gpu.Context(w["grid"]) as ctx:
+            if toggle:
+                ctx.set_option(gpu.OPT_GATHER, gpu.GATHER_BSPLINE)
+                ctx.set_option(gpu.OPT_GATHER, gpu.GATHER_CIC)
+            with pytest.raises(gpu.ScpicError) as e:
+                ctx.get_potential()
+            assert e.value.code == gpu.EINVAL
+            d = _dev(w["parts"])
+            ctx.track(d, w["lattice"], 2)
+            outs.append(_host(d))
+    for k in COORDS + ("lost",):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+    wl = inputs.workload("line_small")
+    with _ctx(gpu, wl["grid"], solver="pipe") as ctx:
+        ctx.set_line_density(wl["line"])
+        d = _dev(wl["parts"])
+        with pytest.raises(gpu.ScpicError) as e:
+            ctx.track(d, wl["lattice"], 1)
+        assert e.value.code == gpu.EUNSUPPORTED
+        with pytest.raises(gpu.ScpicError) as e:
+            ctx.set_option(gpu.OPT_GATHER, 7)
+        assert e.value.code == gpu.EINVAL
