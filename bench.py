@@ -122,7 +122,7 @@ def measured_traffic(n_particles: int):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(w, seconds: float, solver: str = "open"):
+def cpu_baseline(w, seconds: float, solver: str = "open", gather: str = "cic"):
     """The oracle on the host cores: the production lattice's first space-charge
     steps on the full beam, repeated until `seconds` of wall time."""
     import numpy as np
@@ -142,7 +142,7 @@ def cpu_baseline(w, seconds: float, solver: str = "open"):
         if "line" in w:
             oracle.track_line(parts, w["grid"], w["line"], chunk, 1)
         else:
-            oracle.track(parts, w["grid"], chunk, 1, solver=solver)
+            oracle.track(parts, w["grid"], chunk, 1, solver=solver, gather=gather)
         steps += chunk_steps
         el = time.perf_counter() - t0
         if el >= seconds:
@@ -421,7 +421,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, args.cpu_seconds, args.solver)
+        cpu = cpu_baseline(w, args.cpu_seconds, args.solver, args.gather)
 
     out = {
         "metric": "particle-steps/s (push+deposit+solve+kick)",
