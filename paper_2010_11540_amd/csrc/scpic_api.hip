@@ -309,12 +309,16 @@ scpic_status check_line(const scpic_ctx *c, const scpic_particles *p)
     return SCPIC_OK;
 }
 
+// per_element: a scpic_push / scpic_deposit / scpic_kick call, which stays
+// transverse and gathers the field it is given (no line density, no B-spline
+// field); the track and the fused pass take the context's modes.
 scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
-                          const PassOp &op)
+                          const PassOp &op, bool per_element = false)
 {
     const int blocks = blocks_for(c, parts->n, op.deposit);
-    const LineSpec *line = c->line.nz > 0 && (op.kick || op.deposit) ? &c->line : nullptr;
-    const void *bphi = c->bspline && op.kick ? c->sw.phi : nullptr;
+    const LineSpec *line =
+        !per_element && c->line.nz > 0 && (op.kick || op.deposit) ? &c->line : nullptr;
+    const void *bphi = !per_element && c->bspline && op.kick ? c->sw.phi : nullptr;
     hipError_t e = launch_pass(s, to_ptrs(parts), c->geom, op.kick, c->mixed, c->ef, op.kappa,
                                op.els, op.deposit, c->dep, blocks, c->pass_threads, line, bphi);
     if (e != hipSuccess) return fail_hip(e, "particle pass launch");
@@ -725,7 +729,7 @@ scpic_status scpic_push(scpic_ctx *ctx, const scpic_particles *parts,
     std::vector<PassOp> ops;
     emit_segment(ops, false, 0.0, els, false);
     for (const PassOp &op : ops)
-        if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op)) return st;
+        if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, true)) return st;
     return SCPIC_OK;
 }
 
@@ -739,7 +743,7 @@ scpic_status scpic_deposit(scpic_ctx *ctx, const scpic_particles *parts, int64_t
     PassOp op;
     std::memset(&op, 0, sizeof(op));
     op.deposit = true;
-    if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op)) return st;
+    if (scpic_status st = enqueue_pass(ctx, ctx->stream, parts, op, true)) return st;
     const int blocks = parts->n > 0 ? ctx->last_deposit_blocks : 0;
     hipError_t e = launch_reduce(ctx->stream, ctx->dep, blocks, ctx->grid.nx, ctx->grid.ny, rho, n_in);
     if (e != hipSuccess) return fail_hip(e, "reduce launch");
@@ -772,7 +776,7 @@ scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void
     hipError_t e = launch_interleave(ctx->stream, ctx->mixed, true, (void *)ex, (void *)ey, ctx->ef,
                                      ctx->grid.nx * ctx->grid.ny);
     if (e != hipSuccess) return fail_hip(e, "field interleave launch");
-    return enqueue_pass(ctx, ctx->stream, parts, op);
+    return enqueue_pass(ctx, ctx->stream, parts, op, true);
 }
 
 scpic_status scpic_pass(scpic_ctx *ctx, const scpic_particles *parts, int32_t kick, double kappa,

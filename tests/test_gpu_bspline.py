@@ -176,3 +176,22 @@ def test_back_to_cic_and_unsupported_combinations(gpu):
         with pytest.raises(gpu.ScpicError) as e:
             ctx.set_option(gpu.OPT_GATHER, 7)
         assert e.value.code == gpu.EINVAL
+
+
+def test_per_element_kick_gathers_the_given_field(gpu, orc):
+    """scpic_kick with the B-spline gather on still gathers the field it is
+    given: the same result as on a context with the cloud-in-cell gather."""
+    _say("per-element kick with the B-spline gather on")
+    import torch
+    w = inputs.workload("small")
+    q, _ = orc.deposit(inputs.copy_parts(w["parts"]), w["grid"])
+    ex, ey = orc.solve(q, 1.0 / ((1 << 24) * w["n"]), w["grid"])
+    outs = []
+    for gather in (gpu.GATHER_BSPLINE, gpu.GATHER_CIC):
+        with gpu.Context(w["grid"]) as ctx:
+            ctx.set_option(gpu.OPT_GATHER, gather)
+            d = _dev(w["parts"])
+            ctx.kick(d, torch.from_numpy(ex).cuda(), torch.from_numpy(ey).cuda(), 5e-7)
+            outs.append(_host(d))
+    for k in COORDS + ("lost",):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])

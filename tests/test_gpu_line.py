@@ -206,3 +206,30 @@ def test_line_density_off_again_is_plain_pipe_tracking(gpu):
     for k in COORDS6 + ("lost",):
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
     np.testing.assert_array_equal(outs[0]["psigma"], w["parts"]["psigma"])
+
+
+def test_per_element_calls_stay_transverse_with_the_line_on(gpu, orc):
+    """scpic_deposit and scpic_kick ignore the line density: the deposit of
+    four-dimensional particles is the oracle's, and a kick with a given field
+    equals the same kick on a context without the line."""
+    _say("per-element deposit and kick with the line density on")
+    w = inputs.workload("line_small")
+    four = {k: v for k, v in w["parts"].items() if k not in ("sigma", "psigma")}
+    q_ref, n_ref = orc.deposit(inputs.copy_parts(four), w["grid"])
+    ex, ey = orc.solve(q_ref, 1.0 / ((1 << 24) * w["n"]), w["grid"], solver="pipe")
+    import torch
+    outs = []
+    for line_on in (True, False):
+        with gpu.Context(w["grid"]) as ctx:
+            ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_PIPE)
+            if line_on:
+                ctx.set_line_density(w["line"])
+            d = _dev(four)
+            rho, n_in = ctx.deposit(d)
+            np.testing.assert_array_equal(rho.cpu().numpy(), q_ref)
+            assert int(n_in.item()) == n_ref
+            d6 = _dev(w["parts"])
+            ctx.kick(d6, torch.from_numpy(ex).cuda(), torch.from_numpy(ey).cuda(), 3e-7)
+            outs.append(_host(d6))
+    for k in COORDS6 + ("lost",):
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
