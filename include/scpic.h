@@ -114,6 +114,9 @@ typedef struct {
  *                       H0 (a h) with h = L/n, c = 1/sqrt 3, a = (1 - c)/2,
  *                       H0 = (px^2 + py^2)(1 - p_sigma)/2 + p_sigma^2/(2 gamma0^2),
  *                       V = k2 (x^3 - 3 x y^2)/6; k2 = 0 is the exact drift
+ *                       (p[4..15] are ignored; a drift next to a thick
+ *                       sextupole of the same gamma0 may be folded into its
+ *                       first or last H0 flow, which the exact flows allow)
  * The thick elements need the particles' sigma and psigma and are evaluated in
  * FP64 with the device's sin, cos, expm1 and sqrt (results agree with any
  * other correctly implemented evaluation to rounding, not bit for bit).

@@ -282,7 +282,9 @@ __device__ __forceinline__ void quad_thick(const double *__restrict__ m, double 
 // flows of H0 = (px^2 + py^2)(1 - p_sigma)/2 + p_sigma^2/(2 gamma0^2) and of
 // V = k2 (x^3 - 3 x y^2)/6 over the step h = L/n:
 //   H0 (a h), V (h/2), H0 (c h), V (h/2), H0 (a h),  c = 1/sqrt 3, a = (1 - c)/2.
-// k2 = 0 takes the drift in one step.  p_sigma is constant in every element.
+// k2 = 0 takes the drift in one step; m[4] and m[5] are drift lengths the
+// host folded into the first and last H0 flow.  p_sigma is constant in every
+// element.
 __device__ __forceinline__ void apply_element6(int kind, const double *__restrict__ m, double &x,
                                                double &px, double &y, double &py, double &sg,
                                                const Chroma &k)
@@ -291,7 +293,7 @@ __device__ __forceinline__ void apply_element6(int kind, const double *__restric
         quad_thick(m, x, px, y, py, sg, k);
     } else if (kind == SCPIC_EL_SEXT_THICK && m[0] == 0.0) {
         // no sextupole field: the split composes to the exact drift of H0
-        const double L = m[1];
+        const double L = m[1] + m[4] + m[5];
         sg = fma(fma(-0.5 * px, px, fma(-0.5 * py, py, k.psg * m[2])), L, sg);
         x = fma(px * k.q, L, x);
         y = fma(py * k.q, L, y);
@@ -312,12 +314,14 @@ __device__ __forceinline__ void apply_element6(int kind, const double *__restric
             px = fma(-0.5 * tv, fma(X, X, -(Y * Y)), px);
             py = fma(tv * X, Y, py);
         };
+        // folded drifts (host side) lengthen the first and the last H0 flow
+        const double lead = m[4], tail = m[5];
         for (int i = 0; i < n; ++i) {
-            drift(ta);
+            drift(i == 0 ? ta + lead : ta);
             kick();
             drift(tc);
             kick();
-            drift(ta);
+            drift(i == n - 1 ? ta + tail : ta);
         }
     } else {
         apply_element(kind, m, x, px, y, py);

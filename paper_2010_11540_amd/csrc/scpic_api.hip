@@ -241,16 +241,45 @@ scpic_status check_longitudinal(const std::vector<const scpic_element *> &els,
     return SCPIC_OK;
 }
 
+// The elements [begin, end) of v as one pass's kernel arguments.  A thick
+// quadrupole gets its on-momentum rotation computed here.  A drift (a thick
+// sextupole without strength) next to a thick sextupole with the same
+// 1/gamma0^2 is folded into that sextupole's first or last H0 flow, and
+// adjacent drifts into one: the exact flows of H0 compose by adding their
+// lengths, so this changes results only by rounding.  A thick sextupole's
+// p[4] and p[5] carry the folded lead-in and tail lengths.
 PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, size_t end)
 {
     PassElements pe;
     std::memset(&pe, 0, sizeof(pe));
-    pe.n_el = (int32_t)(end - begin);
+    int k = 0;
     for (size_t i = begin; i < end; ++i) {
-        double *m = pe.p[i - begin];
-        pe.kind[i - begin] = v[i]->kind;
+        const int kind = v[i]->kind;
+        double m[16];
         std::memcpy(m, v[i]->p, sizeof(double) * 16);
-        if (v[i]->kind == SCPIC_EL_QUAD_THICK) {
+        if (kind == SCPIC_EL_SEXT_THICK) {
+            m[4] = 0.0;
+            m[5] = 0.0;
+            if (k > 0 && pe.kind[k - 1] == SCPIC_EL_SEXT_THICK && pe.p[k - 1][2] == m[2]) {
+                double *q = pe.p[k - 1];
+                const bool drift = m[0] == 0.0, prev_drift = q[0] == 0.0;
+                if (drift && prev_drift) {
+                    q[1] += m[1];
+                    continue;
+                }
+                if (drift) {  // the tail of the previous sextupole
+                    q[5] += m[1];
+                    continue;
+                }
+                if (prev_drift) {  // the previous drift leads into this sextupole
+                    const double lead = q[1];
+                    std::memcpy(q, m, sizeof(double) * 16);
+                    q[4] = lead;
+                    continue;
+                }
+            }
+        }
+        if (kind == SCPIC_EL_QUAD_THICK) {
             // the on-momentum rotation of both planes, which the kernel
             // corrects per particle for its p_sigma
             const double w0 = std::sqrt(std::fabs(m[0])), phi0 = w0 * m[1];
@@ -260,9 +289,13 @@ PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, siz
             m[6] = std::sinh(phi0);
             m[7] = std::cosh(phi0);
             m[8] = w0 > 0.0 ? 1.0 / w0 : 0.0;
-            for (int k = 9; k < 16; ++k) m[k] = 0.0;
+            for (int j = 9; j < 16; ++j) m[j] = 0.0;
         }
+        pe.kind[k] = kind;
+        std::memcpy(pe.p[k], m, sizeof(double) * 16);
+        ++k;
     }
+    pe.n_el = k;
     return pe;
 }
 
