@@ -234,8 +234,10 @@ __device__ __forceinline__ Chroma chroma(double psg)
 // focusing plane, hyperbolic in the other.  The host supplies phi0 and the
 // four functions at phi0 (m[3..7]) and 1/sqrt|k1| (m[8]); a particle's
 // functions follow from the offset d = phi - phi0 = phi0 (sqrt(q) - 1) by the
-// addition formulas (|d| <= 1/16, i.e. any momentum spread of a real beam), or
-// directly from phi beyond that.  Then
+// addition formulas, with the series of the functions of d for |d| <= 1/16
+// (any momentum spread of a real beam) and beyond that the series of d / 2^h
+// doubled h times (the relative error grows about as 2^h units of rounding:
+// 2^-46 at |d| = 64).  Then
 //   sigma += p_sigma L / gamma0^2 - (1/2) int (px^2 + py^2) ds.
 __device__ __forceinline__ void quad_thick(const double *__restrict__ m, double &x, double &px,
                                            double &y, double &py, double &sg, const Chroma &k)
@@ -255,11 +257,31 @@ __device__ __forceinline__ void quad_thick(const double *__restrict__ m, double 
             shift_angle<false>(d, m[4], m[5], s, c);
             shift_angle<true>(d, m[6], m[7], sh, ch);
         } else {
-            const double phi = phi0 * k.sq;
-            sincos(phi, &s, &c);
-            const double em = expm1(phi), e = em + 1.0;
-            ch = 0.5 * (e + 1.0 / e);
-            sh = 0.5 * (em + em / e);
+            // halve d into the series' range, double the angle back up, then
+            // add phi0 (bounded: an infinite d ends in NaN, not a hang)
+            int h = 0;
+            double dh = d;
+            while (h < 40 && fabs(dh) > 0.0625) {
+                dh *= 0.5;
+                ++h;
+            }
+            shift_angle<false>(dh, 0.0, 1.0, s, c);
+            shift_angle<true>(dh, 0.0, 1.0, sh, ch);
+            for (int r = 0; r < h; ++r) {
+                const double s2 = 2.0 * s * c, c2 = fma(2.0 * c, c, -1.0);
+                const double sh2 = 2.0 * sh * ch, ch2 = fma(2.0 * ch, ch, -1.0);
+                s = s2;
+                c = c2;
+                sh = sh2;
+                ch = ch2;
+            }
+            const double s0 = m[4], c0 = m[5], sh0 = m[6], ch0 = m[7];
+            const double ns = fma(s0, c, c0 * s), nc = fma(c0, c, -(s0 * s));
+            const double nsh = fma(sh0, ch, ch0 * sh), nch = fma(ch0, ch, sh0 * sh);
+            s = ns;
+            c = nc;
+            sh = nsh;
+            ch = nch;
         }
         const double iw = m[8] * k.isq;  // 1 / sqrt(|k1| q)
         const double half_q = 0.5 * k.isq * k.isq;
