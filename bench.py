@@ -381,6 +381,7 @@ def main():
     g1.record(stream)
     torch.cuda.synchronize()
     grid_us = g0.elapsed_time(g1) * 1e3 / args.pass_reps
+
     six = "sigma" in d and bool(np.isin(one_map["kind"], (inputs.QUAD_THICK, inputs.SEXT_THICK)).any())
     line_on = "line" in w
     six = six or line_on
@@ -416,6 +417,38 @@ def main():
             "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
             "flops_per_particle": flops, "hbm_achieved_gbs": round(achieved, 1),
             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)})
+    # the pass's two particle stages alone: the push (the segment's elements,
+    # no kick or deposit) and the interpolation + kick (no elements, no
+    # deposit), each one kernel on the same stream
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        t0_ = torch.cuda.Event(enable_timing=True)
+        t1_ = torch.cuda.Event(enable_timing=True)
+        t0_.record(stream)
+        for _ in range(args.pass_reps):
+            fn()
+        t1_.record(stream)
+        torch.cuda.synchronize()
+        return t0_.elapsed_time(t1_) * 1e3 / args.pass_reps
+
+    no_el = lat[:0]
+    push_us = timed(lambda: ctx.pass_(d2, False, 0.0, one_map, False))
+    kick_us = timed(lambda: ctx.pass_(d2, True, kappa, no_el, False))
+    ext = BYTES_PER_WEIGHT if "w" in d else 0
+    push_bytes = (BYTES_PER_PARTICLE_STEP + (BYTES_PER_LONGITUDINAL if "sigma" in d and six else 0)) * n
+    # read x, y, px, py and write px, py; the line kick also reads sigma, p_sigma, writes p_sigma
+    kick_bytes = (48 + ext + (24 if "line" in w else 0)) * n
+    components = {
+        "push": {"us": round(push_us, 3), "bytes": push_bytes,
+                 "GBps": round(push_bytes / (push_us * 1e-6) / 1e9, 1),
+                 "frac": round(push_bytes / (push_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "kick": {"us": round(kick_us, 3), "bytes": kick_bytes,
+                 "GBps": round(kick_bytes / (kick_us * 1e-6) / 1e9, 1),
+                 "frac": round(kick_bytes / (kick_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "note": ("each stage alone, one kernel per launch, algorithmic bytes; a beam below the "
+                 "256 MB last-level cache can exceed the HBM figure"),
+    }
     del d2
 
     cpu = None
@@ -449,6 +482,7 @@ def main():
             "gpu_event_ms": round(gpu_ms, 3),
         },
         "roofline": roofline,
+        "stages": components,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

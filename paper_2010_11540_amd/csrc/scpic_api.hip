@@ -193,12 +193,17 @@ ParticlePtrs to_ptrs(const scpic_particles *p)
     return r;
 }
 
-int blocks_for(const scpic_ctx *c, int64_t n, bool deposit)
+// Workgroups of a pass over n particles.  A pass that kicks or deposits runs
+// the depositing passes' count (one per compute unit unless set): workgroup b
+// then owns the same particles as in the deposit that wrote header b, whose
+// box sizes its tile and its staged field.  A pure push takes up to eight per
+// compute unit.
+int blocks_for(const scpic_ctx *c, int64_t n, bool lds_pass)
 {
     if (n <= 0) return 0;
     const int64_t need = (n + c->pass_threads - 1) / c->pass_threads;
-    const int64_t cap = deposit ? (c->pass_blocks > 0 ? c->pass_blocks : c->n_cu)
-                                : (int64_t)c->n_cu * 8;
+    const int64_t cap = lds_pass ? (c->pass_blocks > 0 ? c->pass_blocks : c->n_cu)
+                                 : (int64_t)c->n_cu * 8;
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, std::min<int64_t>(cap, c->max_blocks)));
 }
 
@@ -348,7 +353,7 @@ scpic_status check_line(const scpic_ctx *c, const scpic_particles *p)
 scpic_status enqueue_pass(scpic_ctx *c, hipStream_t s, const scpic_particles *parts,
                           const PassOp &op, bool per_element = false)
 {
-    const int blocks = blocks_for(c, parts->n, op.deposit);
+    const int blocks = blocks_for(c, parts->n, op.deposit || op.kick);
     const LineSpec *line =
         !per_element && c->line.nz > 0 && (op.kick || op.deposit) ? &c->line : nullptr;
     const void *bphi = !per_element && c->bspline && op.kick ? c->sw.phi : nullptr;
