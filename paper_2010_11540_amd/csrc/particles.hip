@@ -467,8 +467,9 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 //   DEPOSIT  add the particle's four weights to the workgroup's LDS tile of
 //            the charge grid (nodes outside the tile: global atomics on the
 //            carry grid); particles outside the domain are marked lost.
-// When the whole charge grid fits in LDS it is the tile and gathers read the
-// L2-resident field.  Otherwise the tile covers the box the workgroup's
+// When the whole charge grid fits in LDS and the workgroup's threads have few
+// particles each, the whole grid is the tile and gathers read the L2-resident
+// field.  Otherwise the tile covers the box the workgroup's
 // previous deposit recorded (its header; a workgroup owns the same particles
 // at every step of a track), and that box of the field, which holds every
 // node the kick gathers from, is staged in LDS beside the tile when it fits.
@@ -531,12 +532,15 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         if (KICK && P.w) wp = P.w[p];
     }
 
-    // When the whole charge grid fits in LDS it is the tile, and the kick
-    // gathers from the L2-resident field: the set-up then needs nothing from
-    // the previous pass (no header read, no field staging), only the zeroing
-    // of the tile.  Otherwise the previous pass's header sizes the tile and the
-    // staged field box.
-    const bool whole = DEPOSIT && (size_t)g.nx * g.ny <= lds_bytes / sizeof(uint32_t);
+    // When the whole charge grid fits in LDS and each thread has few
+    // particles, the whole grid is the tile and the kick gathers from the
+    // L2-resident field: the set-up then needs nothing from the previous pass
+    // (no header read, no field staging), only the zeroing of the tile.
+    // Otherwise the previous pass's header sizes the tile and the staged
+    // field box, whose set-up pays off over many particles per thread.
+    constexpr int64_t kWholeMaxPerThread = 4;
+    const bool whole = DEPOSIT && (size_t)g.nx * g.ny <= lds_bytes / sizeof(uint32_t) &&
+                       P.n <= kWholeMaxPerThread * T;
     BlockHeader hd;
     hd.i0 = -1;
     hd.i1 = -2;

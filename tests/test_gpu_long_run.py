@@ -81,3 +81,50 @@ def test_small_workload_1000_turns_mixed_fp64_oracle(gpu, orc):
     for k in runs:
         alive = runs[k]["lost"] == 0
         assert all(np.isfinite(runs[k][c][alive]).all() for c in ("x", "px", "y", "py"))
+
+
+def _perturb(parts, seed):
+    rng = np.random.default_rng(seed)
+    out = inputs.copy_parts(parts)
+    for k in ("x", "px", "y", "py"):
+        out[k] = out[k] * (1.0 + ULP32 * rng.choice([-1.0, 1.0], size=out[k].shape))
+    return out
+
+
+def _run_batch(gpu, w, parts, precision):
+    from paper_2010_11540_amd.scpic import to_device
+    with gpu.Batch(w["grids"], w["offsets"], precision) as b:
+        d = to_device(parts)
+        b.track(d, w["lattices"], TURNS)
+        return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def test_tune_scan_batch_1000_turns_mixed_vs_fp64(gpu):
+    """The 64-beam tune scan (8.1e6 particles) over 1000 turns in the batched
+    mixed and FP64 forms: per beam and plane, the rms emittance of the mixed
+    form against the FP64 form, next to the FP64 form's own response to a
+    2^-24 perturbation of its inputs (one draw).  One draw is a noisy estimate
+    of any single beam's sensitivity, so the bar compares the distributions
+    over the 128 beam-planes: the median and the largest deviation of the
+    mixed form each within twice those of the perturbation (the reading of the
+    small workload's test).  How many beams stay within 1e-4 is printed."""
+    _say("tune scan batch 1000 turns: fp64, fp64 perturbed, mixed")
+    w = inputs.batch_workload()
+    off = w["offsets"]
+    runs = {"fp64": _run_batch(gpu, w, w["parts"], "fp64"),
+            "pert": _run_batch(gpu, w, _perturb(w["parts"], 5), "fp64"),
+            "mixed": _run_batch(gpu, w, w["parts"], "mixed")}
+    dm, dp = [], []
+    for k in range(len(w["grids"])):
+        a, z = int(off[k]), int(off[k + 1])
+        e = {name: _emit({c: v[a:z] for c, v in r.items()}) for name, r in runs.items()}
+        dm.append(np.abs(e["mixed"] / e["fp64"] - 1))
+        dp.append(np.abs(e["pert"] / e["fp64"] - 1))
+    dm, dp = np.array(dm), np.array(dp)
+    worst = int(np.argmax(dm.max(axis=1)))
+    print(f"[batch 1000 turns] mixed vs fp64: max {dm.max():.3e}, median {np.median(dm):.3e}; "
+          f"fp64 response to 2^-24: max {dp.max():.3e}, median {np.median(dp):.3e}; "
+          f"beams within 1e-4: {int((dm.max(axis=1) <= 1e-4).sum())} of {len(dm)} "
+          f"(worst beam {worst}, N={w['sizes'][worst]})", flush=True)
+    assert np.median(dm) <= 2 * np.median(dp), (np.median(dm), np.median(dp))
+    assert dm.max() <= 2 * dp.max(), (dm.max(), dp.max())
