@@ -2,11 +2,16 @@
  * scpic.h -- C ABI of libscpic, a gfx950 (MI355X) library for the per-step 2D
  * particle-in-cell space-charge loop of a proton ring (arXiv:2010.11540):
  *
- *   push    particles through the ring's elements             (Sec. III)
+ *   push    particles through the ring's elements: linear maps and thin
+ *           sextupoles; with (sigma, p_sigma) also the chromatic thick
+ *           quadrupole and the split thick sextupole           (Sec. III)
  *   deposit charge on a transverse grid of nodes              (Sec. IV-A)
- *   solve   the 2D open-boundary Poisson equation for E       (Sec. IV, eq. poisson3D;
- *           Hockney's free-space Green's-function method, cited in Sec. I)
- *   kick    interpolate E to the particles, kick the momenta  (Sec. IV, transverse kick)
+ *   solve   the 2D Poisson equation for E                     (Sec. IV, eq. poisson3D):
+ *           open boundary by Hockney's free-space Green's-function method
+ *           (cited in Sec. I), or the grounded rectangular pipe (Sec. IV-B)
+ *   kick    interpolate E to the particles, kick the momenta  (Sec. IV, transverse kick):
+ *           cloud-in-cell or the B-spline surface of Sec. IV-C; optionally
+ *           with the long-bunch line density and longitudinal kick
  *
  * Conventions
  *   - Every pointer named "device" is HIP device memory owned by the caller;
@@ -22,7 +27,8 @@
  *
  * Units and normalisation
  *   Particles carry (x, px, y, py): positions in m, px, py the transverse
- *   momenta normalised to the reference momentum (rad).  Charge is counted in
+ *   momenta normalised to the reference momentum (rad); optionally the
+ *   longitudinal pair (sigma = s - c beta0 t in m, p_sigma).  Charge is counted in
  *   fixed-point units of 2^-24 of one macro-particle.  The potential solves
  *   lap(phi) = -2 pi rho with the free-space Green's function G = -ln(r), so
  *   a unit line charge has E_r = 1/r; a space-charge kick is p += kappa * E,
@@ -43,7 +49,8 @@ extern "C" {
 typedef int32_t scpic_status;
 #define SCPIC_OK 0
 #define SCPIC_EINVAL (-1)      /* invalid argument; nothing touched */
-#define SCPIC_ENOMEM (-2)      /* device allocation failed (scpic_create only) */
+#define SCPIC_ENOMEM (-2)      /* device allocation failed (only in the calls
+                                  documented to allocate) */
 #define SCPIC_EHIP (-3)        /* a HIP runtime call failed */
 #define SCPIC_EUNSUPPORTED (-4) /* valid but unsupported shape (e.g. grid size) */
 
@@ -146,8 +153,9 @@ const char *scpic_last_error(void);
 
 /* Create a context for one grid geometry and precision form on the current
  * HIP device.  It allocates every workspace (per-block charge partials, FFT
- * spectra, the Green's-function spectrum and the internal field); no call made
- * afterwards allocates device memory.  hip_stream: the hipStream_t to enqueue
+ * spectra, the Green's-function spectrum and the internal field); afterwards
+ * only scpic_set_line_density and SCPIC_OPT_GATHER's first use allocate device
+ * memory (their own buffers), never a push, deposit, solve, kick or track.  hip_stream: the hipStream_t to enqueue
  * on (NULL = the null stream).  The Green's-function spectrum is computed
  * here, once. */
 scpic_status scpic_create(scpic_ctx **out, const scpic_grid *grid, int32_t precision,
@@ -199,7 +207,8 @@ scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void
  * charge is deposited, the field solved with scale 1/(2^24 * parts->n) (the
  * charge of lost particles leaves with them) and every particle kicked with
  * that element's kappa.  Equivalent to the sequence of scpic_push /
- * scpic_deposit / scpic_solve / scpic_kick calls, fused: each kick, the
+ * scpic_deposit / scpic_solve / scpic_kick calls (with the line density or
+ * the B-spline gather on, to the steps those options describe), fused: each kick, the
  * following push and the next deposit run as one pass over the particles, and
  * one turn runs as one captured HIP graph.  Turn graphs are cached per
  * (particle arrays, lattice); at most 8 are kept. */
