@@ -382,15 +382,15 @@ def concat_parts(beams: list[dict]) -> tuple[dict, np.ndarray]:
 
 def batch_workload(n_inst: int = 64, seed: int | None = None, n_min: float = 1e4,
                    n_max: float = 5e5, turns: int = 200, tune_lo: float = 4.05,
-                   tune_hi: float = 4.45) -> dict:
+                   tune_hi: float = 4.45, dnu: float = -0.2) -> dict:
     """A tune scan as one batch of independent beams (the paper's Sec. V scans
     tunes beam by beam).
 
     Beam k: N_k = round(10^U(log10 n_min, log10 n_max)) Gaussian particles
     (the same distribution as the other workloads, its own seed), on a 64^2
     grid over +-6 sigma when N_k < 1e5, else 128^2; its ring is the small
-    workload's (16 segments of 2x2 maps, one SC kick each, kappa for
-    dnu = -0.2) at the tunes (Q_x, Q_y) of point k of an s x s lattice over
+    workload's (16 segments of 2x2 maps, one SC kick each, kappa for the
+    tune shift dnu, -0.2 by default) at the tunes (Q_x, Q_y) of point k of an s x s lattice over
     [tune_lo, tune_hi]^2 (s = ceil(sqrt(n_inst))).  Beams near the integer lose
     particles, which exercises the lost flags and uneven beam sizes."""
     seed = SEED_BASE + 4 if seed is None else seed
@@ -400,7 +400,7 @@ def batch_workload(n_inst: int = 64, seed: int | None = None, n_min: float = 1e4
     side = int(math.ceil(math.sqrt(n_inst)))
     q = np.linspace(tune_lo, tune_hi, side)
     eps = 1e-6
-    kappa = kappa_for_tune_shift(-0.2, eps, 16)
+    kappa = kappa_for_tune_shift(dnu, eps, 16)
     beams, grids, lattices, tunes = [], [], [], []
     for k in range(n_inst):
         qx, qy = q[k % side], q[(k // side) % side]
