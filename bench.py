@@ -106,8 +106,15 @@ def copy_calibration():
                                            "launches": 20}}), flush=True)
 
 
+def code_digest(text: str) -> str:
+    """Digest of a source's code: // comments and blank lines left out, so
+    that editing a comment does not mark a measurement stale."""
+    lines = (l.split("//")[0].rstrip() for l in text.splitlines())
+    return hashlib.sha256("\n".join(l for l in lines if l).encode()).hexdigest()[:16]
+
+
 def source_digest() -> str:
-    return hashlib.sha256(PASS_SOURCE.read_bytes()).hexdigest()[:16]
+    return code_digest(PASS_SOURCE.read_text())
 
 
 def measured_traffic(n_particles: int):

@@ -1,11 +1,14 @@
 // Particle-side kernels of libscpic for gfx950: the fused particle pass
 // (gather + kick, push, cloud-in-cell deposit into an LDS tile of the charge
-// grid) and the copy between split and interleaved field layouts.
+// grid) in its four- and six-dimensional forms, with the long-bunch line
+// density or the B-spline field, single-beam and batched; and the copy
+// between split and interleaved field layouts.
 //
 // Compiled with -ffp-contract=off: every FP64 expression below is evaluated
 // as written, each operation correctly rounded, so the cell index, the
 // fixed-point weights and a linear push are bit-identical to the same IEEE
-// sums evaluated anywhere else.
+// sums evaluated anywhere else.  The thick elements, which have no
+// bit-identical counterpart, use explicit fused multiply-adds.
 #include <algorithm>
 #include <climits>
 #include <vector>
@@ -475,19 +478,19 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // node the kick gathers from, is staged in LDS beside the tile when it fits.
 // At the end each workgroup writes the bounding box of its tile cells to its
 // slice of the partials (no global atomics).
-// MODE is a set of flags.  0: four-dimensional.  1: the particles carry sigma
+// MODE is a set of flags (0: four-dimensional).  1: the particles carry sigma
 // and p_sigma and els may hold thick elements; sigma is loaded and stored with
-// the transverse coordinates.  4: the kick's field is the analytic gradient of
-// the bicubic B-spline surface of the node potential (Sec. IV-C), ef then
-// pointing at the potential on nodes -1..nx by -1..ny.  2: six-dimensional,
-// with the long-bunch line density
-// (Sec. IV): the kick is scaled by lambda/lambda_peak at the particle's sigma
+// the transverse coordinates.  2: six-dimensional, with the long-bunch line
+// density (Sec. IV): the kick is scaled by lambda/lambda_peak at the particle's sigma
 // and p_sigma takes the longitudinal kick -gamma0 kappa phi lambda'/lambda_peak
 // (both tables and the node potential phi from the last solve, interpolated
 // with the particle's line and transverse weights); the deposit adds the
 // particle's two line weights (the one-dimensional form of the charge
 // assignment) to an LDS histogram flushed to the workgroup's row of
 // line.partial.  A particle outside the line is lost like one outside the grid.
+// 4: the kick's field is the analytic gradient of the bicubic B-spline surface
+// of the node potential (Sec. IV-C), ef then pointing at the potential on
+// nodes -1..nx by -1..ny.
 // The body is shared by the single-beam kernel and the batched one: bid is
 // the workgroup's index among the nblk workgroups working on beam P (its
 // slice of the partials and its header), T = nblk * blockDim.x.
