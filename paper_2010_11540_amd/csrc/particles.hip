@@ -406,14 +406,25 @@ struct Box {
     __device__ __forceinline__ int at(int i, int j) const { return (i - i0) * w + (j - j0); }
 };
 
+// Cells of the charge tile around a known box grown by `margin` cells and
+// rounded to 4-column chunks, before any shrinking to a budget.
+__device__ __forceinline__ int tile_cells(const GridGeom &g, const BlockHeader &h, int margin)
+{
+    const int i0 = max(0, h.i0 - margin), i1 = min(g.nx - 1, h.i1 + margin);
+    const int j0 = max(0, h.j0 - margin) & ~3, j1 = min(g.ny - 1, h.j1 + margin) | 3;
+    return (i1 - i0 + 1) * (j1 - j0 + 1);
+}
+
+constexpr int kTileMargin = 12;  // cells around the previous box (particles move)
+
 // Charge tile of a workgroup: the bounding box of its previous deposit grown
-// by a margin (the particles move between steps), rounded to 4-column
+// by `margin` cells (the particles move between steps), rounded to 4-column
 // chunks, clamped to the grid and to the LDS budget; the whole grid when no
 // previous box is known and the grid fits; else as much of the grid's centre
 // as fits.  Cells outside the tile go to the global carry grid instead.
-__device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader &h, size_t budget)
+__device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader &h, size_t budget,
+                                           int margin)
 {
-    constexpr int kMargin = 12;
     const int cap_cells = (int)min(budget / sizeof(uint32_t), (size_t)INT_MAX);
     Box t;
     const bool known = h.i0 >= 0 && h.i0 <= h.i1 && h.j0 >= 0 && h.j0 <= h.j1 && h.i1 < g.nx &&
@@ -427,10 +438,10 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
     }
     int i0, i1, j0, j1;
     if (known) {
-        i0 = max(0, h.i0 - kMargin);
-        i1 = min(g.nx - 1, h.i1 + kMargin);
-        j0 = max(0, h.j0 - kMargin);
-        j1 = min(g.ny - 1, h.j1 + kMargin);
+        i0 = max(0, h.i0 - margin);
+        i1 = min(g.nx - 1, h.i1 + margin);
+        j0 = max(0, h.j0 - margin);
+        j1 = min(g.ny - 1, h.j1 + margin);
     } else {
         i0 = 0;
         i1 = g.nx - 1;
@@ -550,11 +561,28 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     hd.j0 = -1;
     hd.j1 = -2;
     if ((KICK || DEPOSIT) && !whole) hd = dep.header[bid];
+    // The kick stages the field over the previous box (every node it gathers
+    // from) when that box fits in LDS beside the charge tile.
+    const bool known = hd.i0 >= 0 && hd.i0 <= hd.i1 && hd.j0 >= 0 && hd.j0 <= hd.j1 &&
+                       hd.i1 < g.nx && hd.j1 < g.ny;
+    const Box fbox{hd.i0, hd.j0, hd.i1 - hd.i0 + 1, hd.j1 - hd.j0 + 1};
+    const size_t field_bytes =
+        (KICK && !BSPL && !whole && known) ? ((size_t)fbox.h * fbox.w + 2) * sizeof(V) : 0;
     // LDS layout: [charge tile][staged field box + 2 nodes of slack]
     Box tile{0, 0, 0, 0};
     size_t tile_bytes = 0;
     if constexpr (DEPOSIT) {
-        tile = whole ? Box{0, 0, g.nx, g.ny} : charge_tile(g, hd, lds_bytes);
+        // the widest margin (12, 8, 4 or 0 cells) that leaves room for the
+        // field box; 12 when none does
+        int margin = kTileMargin;
+        if (field_bytes) {
+            int m = kTileMargin;
+            while (m >= 0 &&
+                   sizeof(uint32_t) * (size_t)tile_cells(g, hd, m) + field_bytes > lds_bytes)
+                m -= 4;
+            if (m >= 0) margin = m;
+        }
+        tile = whole ? Box{0, 0, g.nx, g.ny} : charge_tile(g, hd, lds_bytes, margin);
         tile_bytes = sizeof(uint32_t) * (size_t)tile.h * tile.w;
     }
     uint32_t *lq = reinterpret_cast<uint32_t *>(lds);
@@ -562,11 +590,8 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     Box ebox{0, 0, 0, 0};
     bool staged = false;
     if constexpr (KICK) {
-        const bool known = hd.i0 >= 0 && hd.i0 <= hd.i1 && hd.j0 >= 0 && hd.j0 <= hd.j1 &&
-                           hd.i1 < g.nx && hd.j1 < g.ny;
-        ebox = Box{hd.i0, hd.j0, hd.i1 - hd.i0 + 1, hd.j1 - hd.j0 + 1};
-        staged = !BSPL && !whole && known &&
-                 ((size_t)ebox.h * ebox.w + 2) * sizeof(V) + tile_bytes <= (size_t)lds_bytes;
+        ebox = fbox;
+        staged = field_bytes && field_bytes + tile_bytes <= (size_t)lds_bytes;
         if (staged) {
             // four nodes per thread per round; indices past the box repeat
             // its last node, so every load and store is unconditional and
