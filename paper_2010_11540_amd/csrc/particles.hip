@@ -502,6 +502,9 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // 4: the kick's field is the analytic gradient of the bicubic B-spline surface
 // of the node potential (Sec. IV-C), ef then pointing at the potential on
 // nodes -1..nx by -1..ny.
+// 8: the four transverse coordinates are streamed with non-temporal loads and
+// stores (particle arrays far larger than the last-level cache, which they
+// would only churn; smaller ones stay cached between passes).
 // The body is shared by the single-beam kernel and the batched one: bid is
 // the workgroup's index among the nblk workgroups working on beam P (its
 // slice of the partials and its header), T = nblk * blockDim.x.
@@ -516,6 +519,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     constexpr bool LINE = (MODE & 2) != 0;
     constexpr bool SIX = (MODE & 1) != 0 || LINE;
     constexpr bool BSPL = (MODE & 4) != 0;
+    constexpr bool NT = (MODE & 8) != 0;
     extern __shared__ __align__(16) unsigned char lds_all[];
     // LDS: [line histogram (MODE 2)][charge tile][staged field box].  The
     // histogram counts in 32 bits: a workgroup adds 4096 per particle and the
@@ -639,10 +643,17 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
         float wn = 1.0f;
         uint8_t lfn = 1;
         if (pn < P.n) {
-            xn = P.x[pn];
-            pxn = P.px[pn];
-            yn = P.y[pn];
-            pyn = P.py[pn];
+            if constexpr (NT) {
+                xn = __builtin_nontemporal_load(&P.x[pn]);
+                pxn = __builtin_nontemporal_load(&P.px[pn]);
+                yn = __builtin_nontemporal_load(&P.y[pn]);
+                pyn = __builtin_nontemporal_load(&P.py[pn]);
+            } else {
+                xn = P.x[pn];
+                pxn = P.px[pn];
+                yn = P.y[pn];
+                pyn = P.py[pn];
+            }
             if constexpr (SIX) {
                 sgn = P.sigma[pn];
                 psgn = P.psigma[pn];
@@ -693,10 +704,17 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                     apply_element(els.kind[e], els.p[e], x, px, y, py);
             }
             if (moves) {
-                P.x[p] = x;
-                P.px[p] = px;
-                P.y[p] = y;
-                P.py[p] = py;
+                if constexpr (NT) {
+                    __builtin_nontemporal_store(x, &P.x[p]);
+                    __builtin_nontemporal_store(px, &P.px[p]);
+                    __builtin_nontemporal_store(y, &P.y[p]);
+                    __builtin_nontemporal_store(py, &P.py[p]);
+                } else {
+                    P.x[p] = x;
+                    P.px[p] = px;
+                    P.y[p] = y;
+                    P.py[p] = py;
+                }
                 if constexpr (SIX) P.sigma[p] = sg;
                 if constexpr (LINE && KICK) P.psigma[p] = psg;
             }
@@ -798,13 +816,14 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     }
 }
 
-template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+// NT: the streamed form (four-dimensional passes only).
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 __global__ void __launch_bounds__(1024)
     k_pass(ParticlePtrs P, GridGeom g, const TE *__restrict__ ef, double kappa,
            PassElements els, DepositTarget dep, unsigned lds_bytes)
 {
-    pass_body<TE, KICK, DEPOSIT, SIX ? 1 : 0>(P, g, ef, kappa, els, dep, lds_bytes,
-                                              (int)blockIdx.x, (int)gridDim.x, LineSpec{});
+    pass_body<TE, KICK, DEPOSIT, (SIX ? 1 : 0) | (NT ? 8 : 0)>(
+        P, g, ef, kappa, els, dep, lds_bytes, (int)blockIdx.x, (int)gridDim.x, LineSpec{});
 }
 
 // The pass with the B-spline field (phi: the node potential on nodes -1..nx
@@ -831,7 +850,7 @@ __global__ void __launch_bounds__(1024)
 // One pass over every beam of a batch: workgroup -> beam from the batch's
 // table, then the same body on that beam's particles, grid, field and
 // partials with its own kick strength and elements (steps[beam]).
-template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 __global__ void __launch_bounds__(1024)
     k_pass_batched(BatchLaunch b, ParticlePtrs all, const BatchStep *__restrict__ steps,
                    unsigned lds_bytes)
@@ -848,7 +867,8 @@ __global__ void __launch_bounds__(1024)
     P.w = all.w ? all.w + I.p0 : nullptr;
     P.lost = all.lost ? all.lost + I.p0 : nullptr;
     P.n = I.n;
-    pass_body<TE, KICK, DEPOSIT, SIX ? 1 : 0>(P, I.g, (const TE *)I.ef, steps[k].kappa,
+    P.stream = NT;
+    pass_body<TE, KICK, DEPOSIT, (SIX ? 1 : 0) | (NT ? 8 : 0)>(P, I.g, (const TE *)I.ef, steps[k].kappa,
                                               steps[k].els, I.dep, lds_bytes,
                                               (int)blockIdx.x - I.pass_block0, I.pass_blocks,
                                               LineSpec{});
@@ -874,14 +894,14 @@ __global__ void __launch_bounds__(256)
 
 size_t g_lds_limit = 0;  // set by prepare_pass_kernels
 
-template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, const void *ef,
                          double kappa, const PassElements &els, const DepositTarget &dep,
                          int blocks, int threads)
 {
     const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
-    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds, s, p,
-                       g, (const TE *)ef, kappa, els, dep, (unsigned)lds);
+    hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads), lds, s,
+                       p, g, (const TE *)ef, kappa, els, dep, (unsigned)lds);
     return hipGetLastError();
 }
 
@@ -907,12 +927,12 @@ hipError_t launch_pass_line_t(hipStream_t s, const ParticlePtrs &p, const GridGe
     return hipGetLastError();
 }
 
-template <typename TE, bool KICK, bool DEPOSIT, bool SIX>
+template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                  const BatchStep *steps, int blocks, int threads)
 {
     const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
-    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds,
+    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads), lds,
                        s, b, all, steps, (unsigned)lds);
     return hipGetLastError();
 }
@@ -927,6 +947,14 @@ void pass_kernels_of(std::vector<const void *> &out)
     out.push_back((const void *)k_pass_batched<TE, false, true, SIX>);
     out.push_back((const void *)k_pass_batched<TE, true, false, SIX>);
     out.push_back((const void *)k_pass_bspline<TE, true, true, SIX>);
+    if (!SIX) {
+        out.push_back((const void *)k_pass<TE, true, true, false, true>);
+        out.push_back((const void *)k_pass<TE, false, true, false, true>);
+        out.push_back((const void *)k_pass<TE, true, false, false, true>);
+        out.push_back((const void *)k_pass_batched<TE, true, true, false, true>);
+        out.push_back((const void *)k_pass_batched<TE, false, true, false, true>);
+        out.push_back((const void *)k_pass_batched<TE, true, false, false, true>);
+    }
     if (SIX) {
         out.push_back((const void *)k_pass_line<TE, true, true>);
         out.push_back((const void *)k_pass_line<TE, false, true>);
@@ -979,6 +1007,14 @@ hipError_t prepare_pass_kernels(size_t lds_limit)
     return kick ? (deposit ? L(double, true, true, false) : L(double, true, false, false))    \
                 : (deposit ? L(double, false, true, false) : L(double, false, false, false))
 
+// The four-dimensional kernels by precision, kick and deposit.
+#define SCPIC_DISPATCH4(L)                                                                \
+    if (mixed)                                                                            \
+        return kick ? (deposit ? L(float, true, true) : L(float, true, false))            \
+                    : (deposit ? L(float, false, true) : L(float, false, false));         \
+    return kick ? (deposit ? L(double, true, true) : L(double, true, false))              \
+                : (deposit ? L(double, false, true) : L(double, false, false))
+
 hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, bool kick,
                        bool mixed, const void *ef, double kappa, const PassElements &els,
                        bool deposit, const DepositTarget &dep, int blocks, int threads,
@@ -1008,6 +1044,12 @@ hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, 
 #undef SCPIC_LL
     }
     const bool six = has_thick(els);
+    if (!six && p.stream) {
+#define SCPIC_L(T, K, D) \
+    launch_pass_t<T, K, D, false, true>(s, p, g, ef, kappa, els, dep, blocks, threads)
+        SCPIC_DISPATCH4(SCPIC_L);
+#undef SCPIC_L
+    }
 #define SCPIC_L(T, K, D, S) launch_pass_t<T, K, D, S>(s, p, g, ef, kappa, els, dep, blocks, threads)
     SCPIC_DISPATCH(SCPIC_L);
 #undef SCPIC_L
@@ -1018,11 +1060,17 @@ hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const Partic
                                bool six, int blocks, int threads)
 {
     if (blocks <= 0) return hipSuccess;
+    if (!six && all.stream) {
+#define SCPIC_L(T, K, D) launch_pass_batched_t<T, K, D, false, true>(s, b, all, steps, blocks, threads)
+        SCPIC_DISPATCH4(SCPIC_L);
+#undef SCPIC_L
+    }
 #define SCPIC_L(T, K, D, S) launch_pass_batched_t<T, K, D, S>(s, b, all, steps, blocks, threads)
     SCPIC_DISPATCH(SCPIC_L);
 #undef SCPIC_L
 }
 #undef SCPIC_DISPATCH
+#undef SCPIC_DISPATCH4
 
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
                              void *ef, int ncell)

@@ -190,6 +190,9 @@ ParticlePtrs to_ptrs(const scpic_particles *p)
     r.w = p->w;
     r.lost = p->lost;
     r.n = p->n;
+    const int64_t bytes_per = 8 * (4 + (p->sigma ? 1 : 0) + (p->psigma ? 1 : 0)) +
+                              (p->w ? 4 : 0) + (p->lost ? 1 : 0);
+    r.stream = p->n > kStreamBytes / bytes_per;
     return r;
 }
 

@@ -72,7 +72,14 @@ struct ParticlePtrs {
     const float *w;  // per-particle kick weight (2.5D line density), may be null
     uint8_t *lost;
     int64_t n;
+    // The arrays are far larger than the last-level cache: the pass streams
+    // the four transverse coordinates with non-temporal loads and stores.
+    bool stream;
 };
+
+// Particle arrays above this many bytes are streamed (half the MI355X's
+// 256 MB last-level cache; below it the arrays stay cached between passes).
+constexpr int64_t kStreamBytes = 128ll << 20;
 
 // Line density of a long bunch (Sec. IV) as a pass sees it: the line of nz
 // nodes z_min + k dz, the node tables of the last solve (lambda/lambda_peak
