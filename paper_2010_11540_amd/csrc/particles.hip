@@ -704,18 +704,26 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                     apply_element(els.kind[e], els.p[e], x, px, y, py);
             }
             if (moves) {
+                // the kick changes only the momenta; the elements move the
+                // particle (a kick-only pass writes px and py alone)
+                const bool shifts = els.n_el > 0;
                 if constexpr (NT) {
-                    __builtin_nontemporal_store(x, &P.x[p]);
+                    if (shifts) {
+                        __builtin_nontemporal_store(x, &P.x[p]);
+                        __builtin_nontemporal_store(y, &P.y[p]);
+                    }
                     __builtin_nontemporal_store(px, &P.px[p]);
-                    __builtin_nontemporal_store(y, &P.y[p]);
                     __builtin_nontemporal_store(py, &P.py[p]);
                 } else {
-                    P.x[p] = x;
+                    if (shifts) {
+                        P.x[p] = x;
+                        P.y[p] = y;
+                    }
                     P.px[p] = px;
-                    P.y[p] = y;
                     P.py[p] = py;
                 }
-                if constexpr (SIX) P.sigma[p] = sg;
+                if constexpr (SIX)
+                    if (shifts) P.sigma[p] = sg;
                 if constexpr (LINE && KICK) P.psigma[p] = psg;
             }
             if constexpr (DEPOSIT) {
