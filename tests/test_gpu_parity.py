@@ -461,6 +461,29 @@ def test_large_workload_full_size_one_step(gpu, orc, precision):
     assert err <= bar, (err, bar)
 
 
+
+def test_large_workload_full_size_two_steps_streamed(gpu, orc):
+    """Two segments of the large workload at full size in FP64: the second
+    pass kicks and deposits with the first pass's boxes known, in the
+    streamed form (the arrays exceed half the last-level cache) and with the
+    charge tile's margin narrowed so the FP64 field box fits beside it.
+    Coordinates against the oracle after both steps and the final kick."""
+    _say("large workload full size (fp64): two steps, streamed fused pass")
+    w = inputs.workload("large")
+    g = w["grid"]
+    lat = w["lattice"][:4]  # map, SC kick, map, SC kick
+    assert list(lat["kind"]) == [inputs.LIN2X2, inputs.SC, inputs.LIN2X2, inputs.SC]
+    ref = inputs.copy_parts(w["parts"])
+    orc.track(ref, g, lat, 1)
+    with gpu.Context(g, "fp64") as ctx:
+        d = _dev(w["parts"])
+        ctx.track(d, lat, 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _turn_err(h, ref)
+    print(f"[large fp64 two steps] coordinate error {err:.3e}", flush=True)
+    assert err <= 1e-10, err
+
 def test_zero_particles_and_no_sc_lattice(gpu, orc):
     _say("track n=0 and lattice without SC")
     g = inputs.make_grid(32)
