@@ -121,6 +121,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy 20 times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--stream-ceiling", action="store_true",
+                    help="only time plain device streams (copies of 320 MiB and 1 GiB, and an "
+                         "in-place scale of four 256 MiB arrays): the read+write bandwidth HBM "
+                         "delivers in practice, beside the 8 TB/s peak")
     return ap.parse_args()
 
 
@@ -135,6 +139,29 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration": {"bytes_read": n * 8, "bytes_written": n * 8,
                                            "launches": 20}}), flush=True)
+
+
+def stream_ceiling():
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    for mib in (320, 1024):
+        n = mib * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        us = stream_time_us(stream, lambda: dst.copy_(src), 50)
+        out[f"copy_{mib}MiB"] = {"us": round(us, 2), "GBps": round(2 * n * 8 / (us * 1e-6) / 1e9, 1)}
+        del src, dst
+    n = 256 * (1 << 20) // 8
+    xs = [torch.rand(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+
+    def scale_all():
+        for x in xs:
+            x.mul_(1.0)
+
+    us = stream_time_us(stream, scale_all, 20)
+    out["scale_4x256MiB"] = {"us": round(us, 2), "GBps": round(8 * n * 8 / (us * 1e-6) / 1e9, 1)}
+    print(json.dumps({"stream_ceiling": out, "peak_GBps": HBM_PEAK_GBS}), flush=True)
 
 
 def code_digest(text: str) -> str:
@@ -337,6 +364,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.stream_ceiling:
+        stream_ceiling()
+        return
     if args.copy_calibration:
         copy_calibration()
         return
