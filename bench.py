@@ -445,12 +445,17 @@ def main():
     achieved = unit_bytes * n / (pass_us * 1e-6) / 1e9
     seg = {"production": "4x4 map", "thick": "FODO cell of thick elements",
            "line": "FODO cell of thick elements, line density"}.get(args.workload, "2x2 map")
+    # the library streams the coordinates of four-dimensional CIC passes over
+    # arrays above 128 MiB (non-temporal loads and stores)
+    array_bytes = n * (8 * sum(k in d for k in ("x", "px", "y", "py", "sigma", "psigma"))
+                       + (4 if "w" in d else 0) + (1 if "lost" in d else 0))
+    streamed = not six and args.gather == "cic" and array_bytes > (128 << 20)
     roofline = {
         "bound": "hbm",
         "kernel": (f"k_pass{'_line' if line_on else ('_bspline' if args.gather == 'bspline' else '')}<"
                    f"{'double' if args.precision == 'fp64' else 'float'},kick,deposit"
-                   f"{',six' if six and not line_on else ''}> (gather+kick, {seg}, CIC deposit, "
-                   "flush)"),
+                   f"{',six' if six and not line_on else ''}{',stream' if streamed else ''}> "
+                   f"(gather+kick, {seg}, CIC deposit, flush)"),
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
