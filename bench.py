@@ -165,10 +165,12 @@ def stream_ceiling():
 
 
 def code_digest(text: str) -> str:
-    """Digest of a source's code: // comments and blank lines left out, so
-    that editing a comment does not mark a measurement stale."""
-    lines = (l.split("//")[0].rstrip() for l in text.splitlines())
-    return hashlib.sha256("\n".join(l for l in lines if l).encode()).hexdigest()[:16]
+    """Digest of a source's code: // comments, line continuations and all
+    whitespace left out, so that editing a comment or re-wrapping a line does
+    not mark a measurement stale."""
+    lines = (l.split("//")[0].rstrip().rstrip("\\") for l in text.splitlines())
+    code = "".join("".join(l.split()) for l in lines)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def source_digest() -> str:

@@ -876,10 +876,9 @@ __global__ void __launch_bounds__(1024)
     P.lost = all.lost ? all.lost + I.p0 : nullptr;
     P.n = I.n;
     P.stream = NT;
-    pass_body<TE, KICK, DEPOSIT, (SIX ? 1 : 0) | (NT ? 8 : 0)>(P, I.g, (const TE *)I.ef, steps[k].kappa,
-                                              steps[k].els, I.dep, lds_bytes,
-                                              (int)blockIdx.x - I.pass_block0, I.pass_blocks,
-                                              LineSpec{});
+    pass_body<TE, KICK, DEPOSIT, (SIX ? 1 : 0) | (NT ? 8 : 0)>(
+        P, I.g, (const TE *)I.ef, steps[k].kappa, steps[k].els, I.dep, lds_bytes,
+        (int)blockIdx.x - I.pass_block0, I.pass_blocks, LineSpec{});
 }
 
 // Between two node arrays (ex, ey) and the internal interleaved layout ef
@@ -940,8 +939,8 @@ hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const Part
                                  const BatchStep *steps, int blocks, int threads)
 {
     const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
-    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads), lds,
-                       s, b, all, steps, (unsigned)lds);
+    hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads),
+                       lds, s, b, all, steps, (unsigned)lds);
     return hipGetLastError();
 }
 
@@ -1069,7 +1068,8 @@ hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const Partic
 {
     if (blocks <= 0) return hipSuccess;
     if (!six && all.stream) {
-#define SCPIC_L(T, K, D) launch_pass_batched_t<T, K, D, false, true>(s, b, all, steps, blocks, threads)
+#define SCPIC_L(T, K, D) \
+    launch_pass_batched_t<T, K, D, false, true>(s, b, all, steps, blocks, threads)
         SCPIC_DISPATCH4(SCPIC_L);
 #undef SCPIC_L
     }

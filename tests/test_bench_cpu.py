@@ -25,6 +25,12 @@ def test_code_digest_ignores_comments_and_blank_lines():
     assert bench.code_digest(code) == bench.code_digest(commented)
 
 
+def test_code_digest_ignores_line_wrapping():
+    one = "#define L(a, b) call(a, b, 1)\nint g() { return f(1, 2, 3); }\n"
+    wrapped = "#define L(a, b) \\\n    call(a, b, 1)\nint g() {\n    return f(1,\n             2, 3);\n}\n"
+    assert bench.code_digest(one) == bench.code_digest(wrapped)
+
+
 def test_code_digest_sees_code_changes():
     a = "int f(int a) {\n    return a + 1;\n}\n"
     b = "int f(int a) {\n    return a + 2;\n}\n"
