@@ -530,6 +530,11 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     lds_bytes -= line_bytes;
     __shared__ int s_box[4];
     __shared__ int s_count;
+    // Six-dimensional passes read their elements' parameters from LDS (one
+    // broadcast read per value) rather than from scalar registers, which the
+    // thick elements' many parameters would otherwise spill.
+    __shared__ double s_el[SIX ? kMaxPassElements * 16 : 1];
+    static_assert(sizeof(s_el) + 256 <= kPassStaticLds, "static LDS beyond the reserved share");
     const int64_t T = (int64_t)nblk * blockDim.x;
     int64_t p = (int64_t)bid * blockDim.x + threadIdx.x;
 
@@ -633,7 +638,10 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             s_count = 0;
         }
     }
-    if (KICK || DEPOSIT) __syncthreads();
+    if constexpr (SIX)
+        for (int t = threadIdx.x; t < els.n_el * 16; t += blockDim.x)
+            s_el[t] = els.p[t >> 4][t & 15];
+    if (KICK || DEPOSIT || SIX) __syncthreads();
 
     const bool moves = KICK || els.n_el > 0;
     int bi0 = INT_MAX, bi1 = -1, bj0 = INT_MAX, bj1 = -1, cnt = 0;
@@ -698,7 +706,7 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
             if constexpr (SIX) {
                 const Chroma ck = chroma(psg);
                 for (int e = 0; e < els.n_el; ++e)
-                    apply_element6(els.kind[e], els.p[e], x, px, y, py, sg, ck);
+                    apply_element6(els.kind[e], s_el + 16 * e, x, px, y, py, sg, ck);
             } else {
                 for (int e = 0; e < els.n_el; ++e)
                     apply_element(els.kind[e], els.p[e], x, px, y, py);
@@ -899,14 +907,21 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-size_t g_lds_limit = 0;  // set by prepare_pass_kernels
+// Dynamic LDS budgets of the four- and six-dimensional passes (the latter
+// keep their element parameters in static LDS); set by prepare_pass_kernels.
+size_t g_lds_limit = 0, g_lds_limit6 = 0;
+template <bool SIX>
+size_t lds_budget()
+{
+    return SIX ? g_lds_limit6 : g_lds_limit;
+}
 
 template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 hipError_t launch_pass_t(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, const void *ef,
                          double kappa, const PassElements &els, const DepositTarget &dep,
                          int blocks, int threads)
 {
-    const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
+    const size_t lds = (KICK || DEPOSIT) ? lds_budget<SIX>() : 0;
     hipLaunchKernelGGL((k_pass<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads), lds, s,
                        p, g, (const TE *)ef, kappa, els, dep, (unsigned)lds);
     return hipGetLastError();
@@ -917,7 +932,7 @@ hipError_t launch_pass_bspline_t(hipStream_t s, const ParticlePtrs &p, const Gri
                                  const void *phi, double kappa, const PassElements &els,
                                  const DepositTarget &dep, int blocks, int threads)
 {
-    const size_t lds = DEPOSIT ? g_lds_limit : 0;
+    const size_t lds = DEPOSIT ? lds_budget<SIX>() : 0;
     hipLaunchKernelGGL((k_pass_bspline<TE, KICK, DEPOSIT, SIX>), dim3(blocks), dim3(threads), lds,
                        s, p, g, (const TE *)phi, kappa, els, dep, (unsigned)lds);
     return hipGetLastError();
@@ -929,8 +944,8 @@ hipError_t launch_pass_line_t(hipStream_t s, const ParticlePtrs &p, const GridGe
                               const DepositTarget &dep, int blocks, int threads,
                               const LineSpec &line)
 {
-    hipLaunchKernelGGL((k_pass_line<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), g_lds_limit,
-                       s, p, g, (const TE *)ef, kappa, els, dep, (unsigned)g_lds_limit, line);
+    hipLaunchKernelGGL((k_pass_line<TE, KICK, DEPOSIT>), dim3(blocks), dim3(threads), g_lds_limit6,
+                       s, p, g, (const TE *)ef, kappa, els, dep, (unsigned)g_lds_limit6, line);
     return hipGetLastError();
 }
 
@@ -938,7 +953,7 @@ template <typename TE, bool KICK, bool DEPOSIT, bool SIX, bool NT = false>
 hipError_t launch_pass_batched_t(hipStream_t s, const BatchLaunch &b, const ParticlePtrs &all,
                                  const BatchStep *steps, int blocks, int threads)
 {
-    const size_t lds = (KICK || DEPOSIT) ? g_lds_limit : 0;
+    const size_t lds = (KICK || DEPOSIT) ? lds_budget<SIX>() : 0;
     hipLaunchKernelGGL((k_pass_batched<TE, KICK, DEPOSIT, SIX, NT>), dim3(blocks), dim3(threads),
                        lds, s, b, all, steps, (unsigned)lds);
     return hipGetLastError();
@@ -978,20 +993,28 @@ bool has_thick(const PassElements &els)
     return false;
 }
 
-// Allow the passes the dynamic LDS they use (beyond the default limit):
-// lds_limit is the device's per-workgroup LDS minus the kernel's static LDS.
-// Called once per context, outside any stream capture.
-hipError_t prepare_pass_kernels(size_t lds_limit)
+// Allow the passes the dynamic LDS they use (beyond the default limit): the
+// device's per-workgroup LDS (lds_per_workgroup) minus the kernels' static
+// LDS, at most 256 bytes for the four-dimensional passes and kPassStaticLds
+// for the six-dimensional ones.  Called once per context, outside any stream
+// capture.
+hipError_t prepare_pass_kernels(size_t lds_per_workgroup)
 {
-    g_lds_limit = lds_limit;
-    std::vector<const void *> kerns;
-    pass_kernels_of<double, false>(kerns);
-    pass_kernels_of<float, false>(kerns);
-    pass_kernels_of<double, true>(kerns);
-    pass_kernels_of<float, true>(kerns);
-    for (const void *k : kerns) {
+    g_lds_limit = lds_per_workgroup - 256;
+    g_lds_limit6 = lds_per_workgroup - kPassStaticLds;
+    std::vector<const void *> four, six;
+    pass_kernels_of<double, false>(four);
+    pass_kernels_of<float, false>(four);
+    pass_kernels_of<double, true>(six);
+    pass_kernels_of<float, true>(six);
+    for (const void *k : four) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_limit);
+                                           (int)g_lds_limit);
+        if (e != hipSuccess) return e;
+    }
+    for (const void *k : six) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)g_lds_limit6);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -655,7 +655,7 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     st = c->mixed ? upload_tables<float>(c) : upload_tables<double>(c);
     if (st) return st;
     // the pass's static LDS is a few words; keep 256 bytes for it
-    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock - 256), "hipFuncSetAttribute");
+    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock), "hipFuncSetAttribute");
     SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     return SCPIC_OK;
 }
@@ -1259,7 +1259,7 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
     b->pass_table = pass_dev;
     SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     if ((st = batch_layout(b, 1024, 1))) return st;
-    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock - 256), "hipFuncSetAttribute");
+    SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock), "hipFuncSetAttribute");
     SCPIC_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
     return SCPIC_OK;
 }

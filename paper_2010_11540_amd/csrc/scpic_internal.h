@@ -18,6 +18,11 @@ constexpr double kChargeOne = 16777216.0;  // 2^24
 
 // Elements a single particle pass can carry in its kernel arguments.
 constexpr int kMaxPassElements = 12;
+// Static LDS a six-dimensional pass may declare (its box and count words and
+// its copy of the element parameters); its dynamic LDS budget is the
+// device's per-workgroup LDS minus this (256 bytes for the four-dimensional
+// passes).
+constexpr int kPassStaticLds = 2048;
 
 // Most split steps a thick sextupole may take.
 constexpr int kMaxSextSteps = 1024;
@@ -144,7 +149,7 @@ hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, 
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
                              void *ef, int ncell);
 
-hipError_t prepare_pass_kernels(size_t lds_bytes);
+hipError_t prepare_pass_kernels(size_t lds_per_workgroup);
 
 // True when els holds a thick element (the pass then needs sigma, p_sigma).
 bool has_thick(const PassElements &els);
