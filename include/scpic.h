@@ -144,6 +144,18 @@ typedef struct {
 
 typedef struct scpic_ctx scpic_ctx;
 
+/* Beam diagnostics over the particles not lost:
+ *   alive    particles with lost == 0 (all of them without a lost array);
+ *   mean     <x>, <px>, <y>, <py> over them;
+ *   emit_x   sqrt(<dx^2><dpx^2> - <dx dpx>^2), d the deviation from the mean
+ *            (population moments, FP64); emit_y likewise in (y, py).
+ * With no particle alive every field is 0. */
+typedef struct {
+    int64_t alive;
+    double mean[4];
+    double emit_x, emit_y;
+} scpic_diag;
+
 /* Library version as 10000*major + 100*minor + patch. */
 int32_t scpic_version(void);
 
@@ -213,7 +225,15 @@ scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void
  * one turn runs as one captured HIP graph.  Turn graphs are cached per
  * (particle arrays, lattice); at most 8 are kept. */
 scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scpic_element *turn,
-                         int32_t n_el, int32_t n_turns);
+                         int32_t n_el, int32_t n_turns, scpic_diag *diag);
+
+/* Diagnostics of parts as they stand (after the work already queued on the
+ * context's stream): two passes over the particles on the device (the sums,
+ * then the centred second moments), each reduced in a fixed order, so the
+ * result does not depend on scheduling.  out: host; the call waits for the
+ * stream.  scpic_track fills its diag argument (host, may be NULL) the same
+ * way after the last turn, and then waits too.  Not for stream capture. */
+scpic_status scpic_diagnose(scpic_ctx *ctx, const scpic_particles *parts, scpic_diag *out);
 
 /* Options (scpic_set_option):
  *   SCPIC_OPT_USE_GRAPH      1 (default): scpic_track replays one HIP graph

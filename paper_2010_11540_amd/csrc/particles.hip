@@ -1103,6 +1103,87 @@ hipError_t launch_pass_batched(hipStream_t s, const BatchLaunch &b, const Partic
 #undef SCPIC_DISPATCH
 #undef SCPIC_DISPATCH4
 
+namespace {
+
+constexpr int kMomentThreads = 256;
+
+// One pass of the beam moments over the alive particles (diagnostics, not on
+// the step's path).  PASS 1 sums 1, x, px, y, py; PASS 2 sums the products
+// of the deviations from the means first[1..4] / first[0].  Each workgroup
+// reduces its threads in a fixed tree and writes part[block][k].
+template <int PASS>
+__global__ void __launch_bounds__(kMomentThreads)
+    k_moments(ParticlePtrs P, const double *__restrict__ first, double *__restrict__ part)
+{
+    double acc[kMoments] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double mx = 0.0, mpx = 0.0, my = 0.0, mpy = 0.0;
+    if (PASS == 2 && first[0] > 0.0) {
+        mx = first[1] / first[0];
+        mpx = first[2] / first[0];
+        my = first[3] / first[0];
+        mpy = first[4] / first[0];
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += stride) {
+        if (P.lost && P.lost[p]) continue;
+        const double x = P.x[p], px = P.px[p], y = P.y[p], py = P.py[p];
+        if (PASS == 1) {
+            acc[0] += 1.0;
+            acc[1] += x;
+            acc[2] += px;
+            acc[3] += y;
+            acc[4] += py;
+        } else {
+            const double dx = x - mx, dpx = px - mpx, dy = y - my, dpy = py - mpy;
+            acc[0] += dx * dx;
+            acc[1] += dpx * dpx;
+            acc[2] += dx * dpx;
+            acc[3] += dy * dy;
+            acc[4] += dpy * dpy;
+            acc[5] += dy * dpy;
+        }
+    }
+    __shared__ double red[kMoments][kMomentThreads];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kMoments; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int h = kMomentThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int k = 0; k < kMoments; ++k) red[k][t] += red[k][t + h];
+        __syncthreads();
+    }
+    if (t < kMoments) part[(size_t)blockIdx.x * kMoments + t] = red[t][0];
+}
+
+// The workgroups' sums added in block order.
+__global__ void __launch_bounds__(64) k_moments_sum(const double *__restrict__ part, int nblocks,
+                                                   double *__restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k < kMoments) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * kMoments + k];
+        out[k] = s;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_moments(hipStream_t s, const ParticlePtrs &p, double *part, double *sums)
+{
+    hipLaunchKernelGGL(k_moments<1>, dim3(kMomentBlocks), dim3(kMomentThreads), 0, s, p,
+                       (const double *)nullptr, part);
+    hipLaunchKernelGGL(k_moments_sum, dim3(1), dim3(64), 0, s, (const double *)part,
+                       kMomentBlocks, sums);
+    hipLaunchKernelGGL(k_moments<2>, dim3(kMomentBlocks), dim3(kMomentThreads), 0, s, p,
+                       (const double *)sums, part);
+    hipLaunchKernelGGL(k_moments_sum, dim3(1), dim3(64), 0, s, (const double *)part,
+                       kMomentBlocks, sums + kMoments);
+    return hipGetLastError();
+}
+
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
                              void *ef, int ncell)
 {

@@ -85,6 +85,9 @@ struct scpic_ctx {
     std::vector<void *> line_mem;
     // kick field from the B-spline surface of the potential (SCPIC_OPT_GATHER)
     bool bspline = false;
+    // scpic_diagnose: per-workgroup moment sums and the two passes' totals
+    double *diag_part = nullptr;
+    double *diag_sums = nullptr;
 
     std::vector<void *> allocations;
     std::vector<GraphEntry> graphs;
@@ -646,6 +649,8 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     ALLOC(c->sw.spec_bx, ce * (size_t)(ny + 1) * nx);
     ALLOC(c->sw.spec_by, ce * (size_t)(ny + 1) * nx);
     ALLOC(c->ef, 2 * fe * ncell);
+    ALLOC(c->diag_part, sizeof(double) * kMomentBlocks * kMoments);
+    ALLOC(c->diag_sums, sizeof(double) * 2 * kMoments);
 #undef ALLOC
     SCPIC_HIP_TRY(hipMemset(c->dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
     // headers start "unknown" (all -1): the first deposit uses the whole grid
@@ -936,8 +941,46 @@ scpic_status scpic_get_line_state(scpic_ctx *ctx, double *lw, double *ld)
     return SCPIC_OK;
 }
 
+static scpic_status track_impl(scpic_ctx *ctx, const scpic_particles *parts,
+                               const scpic_element *turn, int32_t n_el, int32_t n_turns);
+
+scpic_status scpic_diagnose(scpic_ctx *ctx, const scpic_particles *parts, scpic_diag *out)
+{
+    g_last_error.clear();
+    if (scpic_status st = check_ctx(ctx)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (!out) return fail(SCPIC_EINVAL, "out is NULL");
+    *out = scpic_diag{};
+    if (parts->n == 0) return SCPIC_OK;
+    SCPIC_HIP_TRY(launch_moments(ctx->stream, to_ptrs(parts), ctx->diag_part, ctx->diag_sums),
+                  "moments launch");
+    double s[2 * kMoments];
+    SCPIC_HIP_TRY(hipMemcpyAsync(s, ctx->diag_sums, sizeof(s), hipMemcpyDeviceToHost, ctx->stream),
+                  "hipMemcpyAsync");
+    SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    const double a = s[0];
+    if (!(a > 0.0)) return SCPIC_OK;
+    out->alive = (int64_t)a;
+    for (int k = 0; k < 4; ++k) out->mean[k] = s[1 + k] / a;
+    const double *c = s + kMoments;
+    const double ex = (c[0] / a) * (c[1] / a) - (c[2] / a) * (c[2] / a);
+    const double ey = (c[3] / a) * (c[4] / a) - (c[5] / a) * (c[5] / a);
+    out->emit_x = ex > 0.0 ? std::sqrt(ex) : 0.0;
+    out->emit_y = ey > 0.0 ? std::sqrt(ey) : 0.0;
+    return SCPIC_OK;
+}
+
 scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scpic_element *turn,
-                         int32_t n_el, int32_t n_turns)
+                         int32_t n_el, int32_t n_turns, scpic_diag *diag)
+{
+    const scpic_status st = track_impl(ctx, parts, turn, n_el, n_turns);
+    if (st || !diag) return st;
+    return scpic_diagnose(ctx, parts, diag);
+}
+
+// scpic_track without the diagnostics.
+static scpic_status track_impl(scpic_ctx *ctx, const scpic_particles *parts,
+                               const scpic_element *turn, int32_t n_el, int32_t n_turns)
 {
     g_last_error.clear();
     if (scpic_status st = check_ctx(ctx)) return st;

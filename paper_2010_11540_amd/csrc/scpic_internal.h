@@ -145,6 +145,14 @@ hipError_t launch_pass(hipStream_t s, const ParticlePtrs &p, const GridGeom &g, 
                        bool deposit, const DepositTarget &dep, int blocks, int threads,
                        const LineSpec *line = nullptr, const void *bspline_phi = nullptr);
 
+// Beam moments for scpic_diagnose: sums[0..5] = alive count and the sums of
+// x, px, y, py over the alive particles; sums[6..11] = the sums of the
+// centred products dx^2, dpx^2, dx dpx, dy^2, dpy^2, dy dpy.  part: scratch of
+// kMomentBlocks * kMoments doubles.
+constexpr int kMomentBlocks = 256;
+constexpr int kMoments = 6;
+hipError_t launch_moments(hipStream_t s, const ParticlePtrs &p, double *part, double *sums);
+
 // Copy (ex, ey) into the interleaved field ef, or back.
 hipError_t launch_interleave(hipStream_t s, bool mixed, bool to_interleaved, void *ex, void *ey,
                              void *ef, int ncell);

@@ -34,7 +34,7 @@ EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
            "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_autotune",
            "scpic_batch_get_field", "scpic_set_line_density", "scpic_get_line_state",
-           "scpic_get_potential")
+           "scpic_get_potential", "scpic_diagnose")
 
 
 class Grid(ctypes.Structure):
@@ -46,6 +46,15 @@ class Particles(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("px", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("py", ctypes.c_void_p), ("w", ctypes.c_void_p), ("lost", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("sigma", ctypes.c_void_p), ("psigma", ctypes.c_void_p)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("alive", ctypes.c_int64), ("mean", ctypes.c_double * 4),
+                ("emit_x", ctypes.c_double), ("emit_y", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"alive": int(self.alive), "mean": [float(v) for v in self.mean],
+                "emit_x": float(self.emit_x), "emit_y": float(self.emit_y)}
 
 
 class ScpicError(RuntimeError):
@@ -76,7 +85,8 @@ def load_library(path: Path | str | None = None):
     L.scpic_deposit.argtypes = [vp, ctypes.POINTER(Particles), vp, vp]
     L.scpic_solve.argtypes = [vp, vp, dbl, vp, vp]
     L.scpic_kick.argtypes = [vp, ctypes.POINTER(Particles), vp, vp, dbl]
-    L.scpic_track.argtypes = [vp, ctypes.POINTER(Particles), vp, i32, i32]
+    L.scpic_track.argtypes = [vp, ctypes.POINTER(Particles), vp, i32, i32, ctypes.POINTER(Diag)]
+    L.scpic_diagnose.argtypes = [vp, ctypes.POINTER(Particles), ctypes.POINTER(Diag)]
     L.scpic_set_option.argtypes = [vp, i32, i64]
     L.scpic_pass.argtypes = [vp, ctypes.POINTER(Particles), i32, dbl, vp, i32, i32]
     L.scpic_reduce_solve.argtypes = [vp, dbl]
@@ -255,12 +265,25 @@ class Context:
         _check(self._lib.scpic_kick(self._h, ctypes.byref(p), ex.data_ptr(), ey.data_ptr(),
                                     float(kappa)))
 
-    def track(self, parts: dict, lattice, n_turns: int, stream=None):
+    def track(self, parts: dict, lattice, n_turns: int, stream=None, diag: bool = False):
+        """Track n_turns; with diag=True return the beam diagnostics after the
+        last turn (alive count, means, rms emittances; waits for the stream)."""
         self._sync_stream(stream)
         e = _elements(lattice)
         p = particles_struct(parts)
+        out = Diag() if diag else None
         _check(self._lib.scpic_track(self._h, ctypes.byref(p), e.ctypes.data, len(e),
-                                     int(n_turns)))
+                                     int(n_turns), ctypes.byref(out) if diag else None))
+        return out.as_dict() if diag else None
+
+    def diagnose(self, parts: dict, stream=None) -> dict:
+        """Alive count, means of (x, px, y, py) and rms emittances of the
+        particles not lost, computed on the device; waits for the stream."""
+        self._sync_stream(stream)
+        p = particles_struct(parts)
+        out = Diag()
+        _check(self._lib.scpic_diagnose(self._h, ctypes.byref(p), ctypes.byref(out)))
+        return out.as_dict()
 
     def pass_(self, parts: dict, kick: bool, kappa: float, elements, deposit: bool, stream=None):
         self._sync_stream(stream)

@@ -82,7 +82,8 @@ def test_calls_on_null_context_are_einval(lib):
     assert lib.scpic_deposit(None, ctypes.byref(p), None, None) == -1
     assert lib.scpic_solve(None, None, 1.0, None, None) == -1
     assert lib.scpic_kick(None, ctypes.byref(p), None, None, 1.0) == -1
-    assert lib.scpic_track(None, ctypes.byref(p), e.ctypes.data, 1, 1) == -1
+    assert lib.scpic_track(None, ctypes.byref(p), e.ctypes.data, 1, 1, None) == -1
+    assert lib.scpic_diagnose(None, ctypes.byref(p), None) == -1
     assert lib.scpic_set_option(None, 1, 1) == -1
     assert lib.scpic_set_option(None, 4, 1) == -1
     assert lib.scpic_set_stream(None, None) == -1

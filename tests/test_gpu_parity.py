@@ -484,6 +484,56 @@ def test_large_workload_full_size_two_steps_streamed(gpu, orc):
     print(f"[large fp64 two steps] coordinate error {err:.3e}", flush=True)
     assert err <= 1e-10, err
 
+
+def _moments(p):
+    """Alive count, means and rms emittances written out from their
+    definition (population moments about the mean, FP64) over the
+    particles not lost."""
+    m = p["lost"] == 0
+    x, px, y, py = (np.asarray(p[k])[m] for k in ("x", "px", "y", "py"))
+
+    def emit(a, b):
+        da, db = a - a.mean(), b - b.mean()
+        return np.sqrt((da * da).mean() * (db * db).mean() - (da * db).mean() ** 2)
+
+    return int(m.sum()), [v.mean() for v in (x, px, y, py)], emit(x, px), emit(y, py), \
+        [v.std() for v in (x, px, y, py)]
+
+
+def _check_diag(got, p):
+    n, means, ex, ey, stds = _moments(p)
+    assert got["alive"] == n
+    for g_, w_, s_ in zip(got["mean"], means, stds):
+        assert abs(g_ - w_) <= 1e-12 * s_, (g_, w_)
+    assert abs(got["emit_x"] / ex - 1.0) < 1e-11, (got["emit_x"], ex)
+    assert abs(got["emit_y"] / ey - 1.0) < 1e-11, (got["emit_y"], ey)
+
+
+def test_diagnostics_match_their_definition(gpu):
+    """scpic_diagnose, and the diagnostics scpic_track returns after its last
+    turn, against the moments written out in numpy: an off-centre beam with a
+    tenth of its particles lost, then the same beam after two turns; the two
+    calls on the same arrays agree exactly (fixed-order reductions)."""
+    _say("beam diagnostics vs their definition")
+    w = inputs.workload("small")
+    parts = inputs.copy_parts(w["parts"])
+    rng = np.random.Generator(np.random.PCG64(inputs.SEED_BASE + 77))
+    parts["lost"][rng.random(parts["x"].shape[0]) < 0.1] = 1
+    parts["x"] = parts["x"] + 0.3 * parts["x"].std()
+    parts["py"] = parts["py"] - 0.2 * parts["py"].std()
+    with gpu.Context(w["grid"]) as ctx:
+        d = _dev(parts)
+        _check_diag(ctx.diagnose(d), parts)
+        tracked = ctx.track(d, w["lattice"], 2, diag=True)
+        _check_diag(tracked, _host(d))
+        assert ctx.diagnose(d) == tracked
+        none = _dev(inputs.gaussian_beam(0, 1))
+        assert ctx.diagnose(none) == {"alive": 0, "mean": [0.0] * 4, "emit_x": 0.0,
+                                      "emit_y": 0.0}
+        gone = inputs.gaussian_beam(500, 3)
+        gone["lost"][:] = 1
+        assert ctx.diagnose(_dev(gone))["alive"] == 0
+
 def test_zero_particles_and_no_sc_lattice(gpu, orc):
     _say("track n=0 and lattice without SC")
     g = inputs.make_grid(32)
