@@ -232,7 +232,10 @@ scpic_status scpic_track(scpic_ctx *ctx, const scpic_particles *parts, const scp
  * then the centred second moments), each reduced in a fixed order, so the
  * result does not depend on scheduling.  out: host; the call waits for the
  * stream.  scpic_track fills its diag argument (host, may be NULL) the same
- * way after the last turn, and then waits too.  Not for stream capture. */
+ * way after the last turn, and then waits too.  Not for stream capture.
+ * The emittance is the usual rms definition, not an equation of the paper.
+ * Errors: SCPIC_EINVAL for a NULL context, particle set or out (checked
+ * before any device work); SCPIC_EHIP if a launch or the copy fails. */
 scpic_status scpic_diagnose(scpic_ctx *ctx, const scpic_particles *parts, scpic_diag *out);
 
 /* Options (scpic_set_option):
