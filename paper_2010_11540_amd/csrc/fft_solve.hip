@@ -112,7 +112,7 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw,
 
 constexpr int kRowThreads = 1024;  // row-forward: 16 waves share the reduction
 constexpr int kColThreads = 128;   // columns: two waves, one per inverse transform
-constexpr int kInvThreads = 64;    // row-inverse: one wave
+constexpr int kInvThreads = 256;   // row-inverse: loads and stores over 4 waves
 constexpr int kMaxPerThread = kMaxFft / 64;
 
 // Exact sum of grid row i over the partials of nblocks workgroups plus the
