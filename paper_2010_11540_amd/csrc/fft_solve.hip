@@ -111,7 +111,7 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw,
 }
 
 constexpr int kRowThreads = 1024;  // row-forward: 16 waves share the reduction
-constexpr int kColThreads = 128;   // columns: two waves, one per inverse transform
+constexpr int kColThreads = 256;   // columns: 4 waves; waves 0 and 1 run the inverse transforms
 constexpr int kInvThreads = 256;   // row-inverse: loads and stores over 4 waves
 constexpr int kMaxPerThread = kMaxFft / 64;
 
@@ -435,10 +435,12 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     const int wave = tid >> 6, lane = tid & 63;
     cx<T> *in = wave ? d : c;
     cx<T> *tmp = wave ? b : a;
-    const cx<T> *res = fft_lds(in, tmp, mx, log2mx, twl, 1, lane, 64);
+    // waves 2 and 3 (loads and the forward transform only) pass a lane index
+    // past every butterfly, so they only keep the barriers
+    const cx<T> *res = fft_lds(in, tmp, mx, log2mx, twl, 1, wave < 2 ? lane : mx, 64);
     if (wave == 0) {
         for (int i = lane; i < nx; i += 64) bx[(size_t)i * (ny + 1) + l] = conj(res[i]);
-    } else {
+    } else if (wave == 1) {
         for (int i = lane; i < nx; i += 64)
             by[(size_t)i * (ny + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
         if (bp)
