@@ -15,13 +15,20 @@ Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 and the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+K and W are lower bounds in space-charge steps: both are rounded up to whole
+turns (a track call runs whole turns), the timed region to at least ten turns
+of the production ring so that replays of the captured turn graph dominate it;
+the line reports the steps actually timed and the ones requested.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
+import platform
 import sys
 import time
 from pathlib import Path
@@ -29,6 +36,8 @@ from pathlib import Path
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
+METRIC = ("particle-steps/sec (push+deposit+solve+kick), 1e6 particles, 128\u00b2 grid; "
+          "% HBM peak")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64  # read + write x, px, y, py in FP64
 BYTES_PER_WEIGHT = 4          # + the FP32 line-density kick weight (2.5D long bunch)
@@ -96,11 +105,11 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed SC steps, a multiple of the steps per turn (default: 1000 for "
-                         "production, 20 turns otherwise)")
+                    help="timed SC steps, at least; rounded up to whole turns and to the "
+                         "workload's minimum (default: 20 turns of production, 20 otherwise)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed SC steps before timing (default: 200 for production, 2 turns "
-                         "otherwise)")
+                    help="untimed SC steps before timing, at least; rounded up to whole turns, "
+                         "two at the least (default: 2 turns)")
     ap.add_argument("--workload", default="production",
                     choices=["production", "small", "large", "batch", "thick", "line"],
                     help="production (the metric): 1e6 Gaussian, 128^2; large: 1e7 KV long "
@@ -115,8 +124,8 @@ def parse():
     ap.add_argument("--pass-threads", type=int, default=0)
     ap.add_argument("--pass-blocks", type=int, default=0)
     ap.add_argument("--pass-reps", type=int, default=200, help="standalone pass launches timed")
-    ap.add_argument("--cpu-seconds", type=float, default=6.0,
-                    help="wall-clock budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="wall-clock budget of each CPU oracle sample (all host threads, then one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 64 MiB device-to-device copy 20 times (the known-size "
@@ -190,8 +199,9 @@ def measured_traffic(n_particles: int):
 
 
 def cpu_baseline(w, seconds: float, solver: str = "open", gather: str = "cic"):
-    """The oracle on the host cores: the production lattice's first space-charge
-    steps on the full beam, repeated until `seconds` of wall time."""
+    """The oracle on the host cores, on every thread and on one: the ring's
+    first space-charge steps on the whole beam, repeated until `seconds` of
+    wall time each."""
     import numpy as np
 
     import oracle
@@ -202,25 +212,28 @@ def cpu_baseline(w, seconds: float, solver: str = "open", gather: str = "cic"):
     chunk_steps = min(5, len(sc_idx))
     chunk = lat[: sc_idx[chunk_steps - 1] + 1]
     parts = inputs.copy_parts(w["parts"])
-    oracle.lib()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
+
+    def run_chunk():
         if "line" in w:
             oracle.track_line(parts, w["grid"], w["line"], chunk, 1)
         else:
             oracle.track(parts, w["grid"], chunk, 1, solver=solver, gather=gather)
-        steps += chunk_steps
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+        return w["n"] * chunk_steps
+
+    full, one = cpu_both(run_chunk, seconds)
     return {
-        "value": w["n"] * steps / el,
+        "value": full["value"],
         "unit": "particle-steps/s",
-        "cores": oracle.num_threads(),
+        "cores": full["threads"],
         "kind": "oracle",
-        "sample": f"{steps} SC steps (first {chunk_steps} segments of the turn, repeated) on all "
-                  f"{w['n']} particles of the {w['name']} workload, {el:.1f} s wall",
+        "sample": (f"the first {chunk_steps} SC steps of the turn on all {w['n']} particles of the "
+                   f"{w['name']} workload, repeated: {full['particle_steps'] // w['n']} steps in "
+                   f"{full['wall_s']:.1f} s on {full['threads']} threads, "
+                   f"{one['particle_steps'] // w['n']} steps in {one['wall_s']:.1f} s on 1"),
+        "value_1thread": one["value"],
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "note": CPU_NOTE,
     }
 
 
@@ -242,46 +255,124 @@ WORKLOAD_TEXT = {
 }
 
 
-def default_steps(args, steps_per_turn: int):
-    if args.steps is None:
-        args.steps = 1000 if args.workload == "production" else 20 * steps_per_turn
-    if args.warmup is None:
-        args.warmup = 200 if args.workload == "production" else 2 * steps_per_turn
+# Whole turns timed and warmed up.  A track call launches its first turn
+# directly and replays the captured graph of a steady turn for the others, so
+# the timed call needs many turns for the replays to dominate it; the warm-up
+# call (two turns at least) captures that graph.
+MIN_TIMED_TURNS = {"production": 10, "batch": 5, "small": 10}
+DEFAULT_TIMED_TURNS = {"production": 20}
+MIN_WARMUP_TURNS = 2
+
+
+def resolve_turns(workload: str, steps, warmup, steps_per_turn: int) -> dict:
+    """Turns to time and to warm up for requested SC step counts.  Each
+    request is a lower bound: rounded up to whole turns and to the workload's
+    minimum (None takes the default).  Any integer is accepted."""
+    spt = max(1, int(steps_per_turn))
+    min_timed = MIN_TIMED_TURNS.get(workload, 2)
+    if steps is None:
+        timed = DEFAULT_TIMED_TURNS.get(workload, 20)
+    else:
+        timed = max(min_timed, math.ceil(max(0, int(steps)) / spt))
+    if warmup is None:
+        warm = MIN_WARMUP_TURNS
+    else:
+        warm = max(MIN_WARMUP_TURNS, math.ceil(max(0, int(warmup)) / spt))
+    return {"timed_turns": timed, "warmup_turns": warm, "steps": timed * spt,
+            "warmup": warm * spt, "steps_requested": steps, "warmup_requested": warmup,
+            "steps_per_turn": spt}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine() or "unknown"
+
+
+def timed_rate(run_chunk, seconds: float) -> tuple[float, int, float]:
+    """Call run_chunk() (which returns the particle-steps it did) until
+    `seconds` of wall time have passed: (particle-steps/s, particle-steps,
+    seconds)."""
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        done += run_chunk()
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return done / el, done, el
+
+
+# Particles lost on the way take no further part, so the metric counts the
+# alive ones: value = sum over timed steps of the alive count / wall time.
+# Lost flags are sticky, so the count after the timed region, times the steps,
+# is a lower bound on that sum, and exact when nothing was lost meanwhile.
+ALIVE_NOTE = ("sum over the timed steps of the particles alive, taken as steps x alive_after: a "
+              "lower bound, exact when alive_before == alive_after")
+
+CPU_NOTE = ("the oracle is plain FP64 C with OpenMP over particles and target nodes; its open-"
+            "boundary solve is the direct sum of the Green's function over every charged node "
+            "(O(nodes^2) per step, no FFT), which takes most of its time")
+
+
+def cpu_both(run_chunk, seconds: float) -> tuple[dict, dict]:
+    """The oracle's rate on every host thread, then on one thread."""
+    import oracle
+
+    oracle.lib()
+    threads = oracle.num_threads()
+    v_all, done_all, el_all = timed_rate(run_chunk, seconds)
+    oracle.set_num_threads(1)
+    try:
+        v_one, done_one, el_one = timed_rate(run_chunk, seconds)
+    finally:
+        oracle.set_num_threads(threads)
+    return ({"value": v_all, "threads": threads, "particle_steps": done_all, "wall_s": el_all},
+            {"value": v_one, "threads": 1, "particle_steps": done_one, "wall_s": el_one})
 
 
 def cpu_baseline_batch(w, seconds: float):
-    """The oracle on the host cores: each beam of the tune scan in turn through
-    its first 5 space-charge steps, until `seconds` of wall time."""
+    """The oracle on the host cores, on every thread and on one: each beam of
+    the tune scan in turn through its first 5 space-charge steps, until
+    `seconds` of wall time each."""
     import numpy as np
 
     import oracle
     from paper_2010_11540_amd import inputs
 
-    oracle.lib()
-    done = 0
-    beams = 0
-    t0 = time.perf_counter()
-    k = 0
-    while True:
+    state = {"k": 0, "beams": 0}
+
+    def run_chunk():
+        k = state["k"]
         a, b = int(w["offsets"][k]), int(w["offsets"][k + 1])
         lat = w["lattices"][k]
         sc_idx = np.nonzero(lat["kind"] == inputs.SC)[0]
         chunk = lat[: sc_idx[4] + 1]
         parts = {key: v[a:b].copy() for key, v in w["parts"].items()}
         oracle.track(parts, w["grids"][k], chunk, 1)
-        done += (b - a) * 5
-        beams += 1
-        k = (k + 1) % len(w["grids"])
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
+        state["k"] = (k + 1) % len(w["grids"])
+        state["beams"] += 1
+        return (b - a) * 5
+
+    full, one = cpu_both(run_chunk, seconds)
     return {
-        "value": done / el,
+        "value": full["value"],
         "unit": "particle-steps/s",
-        "cores": oracle.num_threads(),
+        "cores": full["threads"],
         "kind": "oracle",
-        "sample": f"first 5 SC steps of {beams} beams of the tune scan (one after another), "
-                  f"{done} particle-steps, {el:.1f} s wall",
+        "sample": (f"the first 5 SC steps of the tune scan's beams one after another: "
+                   f"{full['particle_steps']} particle-steps in {full['wall_s']:.1f} s on "
+                   f"{full['threads']} threads, {one['particle_steps']} in {one['wall_s']:.1f} s "
+                   f"on 1 ({state['beams']} beams in all)"),
+        "value_1thread": one["value"],
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "note": CPU_NOTE,
     }
 
 
@@ -292,34 +383,31 @@ def run_batch(args):
 
     w = inputs.batch_workload()
     steps_per_turn = 16
-    default_steps(args, steps_per_turn)
-    if args.steps % steps_per_turn or args.warmup % steps_per_turn:
-        print(f"--steps and --warmup must be multiples of {steps_per_turn} (one turn)",
-              file=sys.stderr)
-        sys.exit(2)
+    plan = resolve_turns("batch", args.steps, args.warmup, steps_per_turn)
     b = scpic.Batch(w["grids"], w["offsets"], args.precision)
     d = scpic.to_device(w["parts"])
     torch.cuda.synchronize()
     threads, per_cu = b.autotune(d, w["lattices"], trial_turns=2)
     print(f"[bench] autotuned pass shape: {threads} threads, {per_cu} workgroups per CU",
           file=sys.stderr, flush=True)
-    if args.warmup:
-        b.track(d, w["lattices"], args.warmup // steps_per_turn)
+    b.track(d, w["lattices"], plan["warmup_turns"])
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done ({plan['warmup']} steps)", file=sys.stderr, flush=True)
+    n = w["n"]
+    alive_before = int((d["lost"] == 0).sum().item())
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    b.track(d, w["lattices"], args.steps // steps_per_turn)
+    b.track(d, w["lattices"], plan["timed_turns"])
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
-    print(f"[bench] timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
+    print(f"[bench] timed {plan['steps']} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
           file=sys.stderr, flush=True)
-    n = w["n"]
     alive = int((d["lost"] == 0).sum().item())
     cpu = None
     if not args.no_cpu:
@@ -327,12 +415,14 @@ def run_batch(args):
         cpu = cpu_baseline_batch(w, args.cpu_seconds)
     out = {
         "metric": "particle-steps/s (push+deposit+solve+kick)",
-        "value": n * args.steps / wall,
+        "value": alive * plan["steps"] / wall,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": plan["steps"],
+        "warmup": plan["warmup"],
+        "steps_requested": plan["steps_requested"],
+        "warmup_requested": plan["warmup_requested"],
+        "ms_per_step": wall * 1e3 / plan["steps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -341,7 +431,8 @@ def run_batch(args):
         "config": {"workload": WORKLOAD_TEXT["batch"], "particles": n, "beams": len(w["grids"]),
                    "sc_steps_per_turn": steps_per_turn, "precision": args.precision,
                    "graph": True, "pass_threads": threads, "pass_workgroups_per_cu": per_cu,
-                   "alive_after": alive, "gpu_event_ms": round(gpu_ms, 3)},
+                   "alive_before": alive_before, "alive_after": alive,
+                   "value_counts": ALIVE_NOTE, "gpu_event_ms": round(gpu_ms, 3)},
         "roofline": None,
         "cpu_baseline": cpu,
     }
@@ -378,11 +469,7 @@ def main():
     w = inputs.workload(args.workload)
     lat = w["lattice"]
     steps_per_turn = int((lat["kind"] == inputs.SC).sum())
-    default_steps(args, steps_per_turn)
-    if args.steps % steps_per_turn or args.warmup % steps_per_turn:
-        print(f"--steps and --warmup must be multiples of {steps_per_turn} (one turn)",
-              file=sys.stderr)
-        sys.exit(2)
+    plan = resolve_turns(args.workload, args.steps, args.warmup, steps_per_turn)
     n = w["n"]
     ctx = scpic.Context(w["grid"], args.precision)
     if "solver" in w:
@@ -402,10 +489,10 @@ def main():
     d = scpic.to_device(w["parts"])
     torch.cuda.synchronize()
 
-    if args.warmup:
-        ctx.track(d, lat, args.warmup // steps_per_turn)
+    ctx.track(d, lat, plan["warmup_turns"])
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done ({plan['warmup']} steps)", file=sys.stderr, flush=True)
+    alive_before = int((d["lost"] == 0).sum().item())
 
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -413,16 +500,16 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    ctx.track(d, lat, args.steps // steps_per_turn)
+    ctx.track(d, lat, plan["timed_turns"])
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
-    print(f"[bench] timed {args.steps} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
+    print(f"[bench] timed {plan['steps']} steps: {wall * 1e3:.1f} ms wall, {gpu_ms:.1f} ms events",
           file=sys.stderr, flush=True)
     seconds = wall
-    value = n * args.steps / seconds
     alive = int((d["lost"] == 0).sum().item())
+    value = alive * plan["steps"] / seconds
 
     # dominant kernel: the fused pass (kick + the elements of the turn's first
     # segment + deposit), timed alone on the same stream over a copy of the beam
@@ -509,13 +596,16 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds, args.solver, args.gather)
 
     out = {
-        "metric": "particle-steps/s (push+deposit+solve+kick)",
+        "metric": METRIC if args.workload == "production" else
+                  "particle-steps/s (push+deposit+solve+kick)",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": seconds * 1e3 / args.steps,
+        "steps": plan["steps"],
+        "warmup": plan["warmup"],
+        "steps_requested": plan["steps_requested"],
+        "warmup_requested": plan["warmup_requested"],
+        "ms_per_step": seconds * 1e3 / plan["steps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -530,9 +620,12 @@ def main():
             "solver": args.solver,
             "gather": args.gather,
             "graph": not args.no_graph,
+            "alive_before": alive_before,
             "alive_after": alive,
+            "value_counts": ALIVE_NOTE,
             "gpu_event_ms": round(gpu_ms, 3),
         },
+        "step_hbm_frac": round(BYTES_PER_PARTICLE_STEP * value / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roofline,
         "stages": components,
         "cpu_baseline": cpu,

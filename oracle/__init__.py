@@ -73,11 +73,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not _LIB.exists():
-            build()
+        build(force=False)
         L = ctypes.CDLL(str(_LIB))
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
         L.orc_num_threads.restype = i32
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = i32
         L.orc_push.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp]
         L.orc_push.restype = i32
         L.orc_deposit.argtypes = [i64, vp, vp, vp, i32, i32, dbl, dbl, dbl, dbl, vp]
@@ -147,6 +148,11 @@ def _elements(elements):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> int:
+    """OpenMP threads of later oracle calls (timing only); returns the count in effect."""
+    return lib().orc_set_num_threads(int(n))
 
 
 def _longitudinal(parts):

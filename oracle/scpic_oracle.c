@@ -79,6 +79,18 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the following parallel regions (n >= 1); returns the count in
+ * effect afterwards.  Timing only: results do not depend on it. */
+int orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return orc_num_threads();
+}
+
 /* ------------------------------------------------------------------------ */
 /* Single-particle mechanics (Sec. III): each element is a symplectic map.   */
 /* ------------------------------------------------------------------------ */
