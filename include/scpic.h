@@ -67,7 +67,9 @@ typedef int32_t scpic_status;
  * index i*ny + j (i along x).  A particle belongs to the domain when
  * 0 <= (x - x_min) * (1/dx) < nx - 1 and likewise in y (each product and the
  * reciprocal evaluated in FP64, correctly rounded); a NaN coordinate does not.
- * Supported: nx, ny powers of two in [8, 256]. */
+ * Supported: nx in [8, 256], ny a multiple of 4 in [8, 256] (the paper's
+ * 100 x 100 grid, Sec. IV-A, among them); the grounded pipe solver
+ * (SCPIC_OPT_SOLVER) needs powers of two.  Other sizes: SCPIC_EUNSUPPORTED. */
 typedef struct {
     int32_t nx, ny;
     double x_min, y_min, dx, dy;
@@ -164,7 +166,10 @@ int32_t scpic_version(void);
 const char *scpic_last_error(void);
 
 /* Create a context for one grid geometry and precision form on the current
- * HIP device.  It allocates every workspace (per-block charge partials, FFT
+ * HIP device: the cells and representative grid points of the particle-in-cell
+ * cycle (Sec. I), here the transverse node grid of the charge density and the
+ * Poisson solve (Sec. IV, Sec. IV-A: the grid sized so that one copy of the
+ * charge grid sits in on-chip memory).  It allocates every workspace (per-block charge partials, FFT
  * spectra, the Green's-function spectrum and the internal field); afterwards
  * only scpic_set_line_density and SCPIC_OPT_GATHER's first use allocate device
  * memory (their own buffers), never a push, deposit, solve, kick or track.  hip_stream: the hipStream_t to enqueue
@@ -200,7 +205,8 @@ scpic_status scpic_deposit(scpic_ctx *ctx, const scpic_particles *parts, int64_t
 /* Open-boundary field of a charge grid: the potential is the linear
  * convolution of rho*scale with G(X,Y) = -ln(X^2+Y^2)/2 over node offsets
  * (G(0,0) = the average of G over one cell), taken by a zero-padded
- * 2nx x 2ny FFT convolution; the field is the centred difference
+ * mx x my FFT convolution (mx, my the smallest powers of two >= 2nx, 2ny);
+ * the field is the centred difference
  *   ex = -(phi[i+1][j] - phi[i-1][j]) / (2 dx),  ey likewise,
  * at the nodes 0..nx-1 x 0..ny-1 (both evaluated spectrally).
  * rho: device, nx*ny int64.  ex, ey: device, nx*ny, double (SCPIC_FP64) or
@@ -214,8 +220,13 @@ scpic_status scpic_solve(scpic_ctx *ctx, const int64_t *rho, double scale, void 
 scpic_status scpic_kick(scpic_ctx *ctx, const scpic_particles *parts, const void *ex,
                         const void *ey, double kappa);
 
-/* Track n_turns through the one-turn sequence turn[0..n_el) (host array):
- * non-SC elements are pushed in order; at each SCPIC_EL_SC element the beam's
+/* Track n_turns through the one-turn sequence turn[0..n_el) (host array).
+ * This is the particle-in-cell cycle of Sec. I repeated over the ring's
+ * components and turns: charge assignment, Poisson solve, then motion in
+ * the solved field, with the single-particle maps of Sec. III between the
+ * space-charge locations and the space-charge kick of Sec. IV (its length L
+ * the distance since the previous location, carried by kappa).
+ * Non-SC elements are pushed in order; at each SCPIC_EL_SC element the beam's
  * charge is deposited, the field solved with scale 1/(2^24 * parts->n) (the
  * charge of lost particles leaves with them) and every particle kicked with
  * that element's kappa.  Equivalent to the sequence of scpic_push /
@@ -247,7 +258,8 @@ scpic_status scpic_diagnose(scpic_ctx *ctx, const scpic_particles *parts, scpic_
  *                            (256, 512 or 1024; default 1024).
  *   SCPIC_OPT_SOLVER         SCPIC_SOLVER_OPEN (default): the open-boundary
  *                            convolution of scpic_solve's comment;
- *                            SCPIC_SOLVER_PIPE: the grounded rectangular pipe
+ *                            SCPIC_SOLVER_PIPE (nx and ny powers of two, else
+ *                            SCPIC_EUNSUPPORTED): the grounded rectangular pipe
  *                            of Sec. IV-B -- the 5-point discrete Poisson
  *                            equation lap phi = -2 pi rho / (dx dy) with
  *                            phi = 0 on walls through node 0 and node nx along
@@ -373,7 +385,10 @@ scpic_status scpic_batch_destroy(scpic_batch *b);
 scpic_status scpic_batch_set_stream(scpic_batch *b, void *hip_stream);
 
 /* Track every beam n_turns turns through its own ring, as scpic_track does
- * for one beam (same kick placement, same normalisation 1/(2^24 N0_k) with
+ * for one beam: the particle-in-cell cycle of Sec. I with the maps of
+ * Sec. III and the kick of Sec. IV, for independent beams such as the
+ * points of a tune scan (Sec. V compares tunes and their spread across
+ * settings).  Same kick placement, same normalisation 1/(2^24 N0_k) with
  * N0_k = offsets[k+1] - offsets[k], same lost-particle rules).
  * parts: the concatenated beams (parts->n == offsets[n_inst]; w and lost
  * may be NULL).  turns[k]: host array of n_els[k] elements, beam k's ring.

@@ -1,21 +1,23 @@
 // Grid-side kernels of libscpic for gfx950: the exact reduction of the
 // per-workgroup charge partials and the open-boundary Poisson solve as a
-// zero-padded (2nx x 2ny) FFT convolution with the free-space Green's function
-// (Hockney's method), the centred-difference field taken in the spectrum.
-// Hand-written radix-4/2 Stockham FFTs in LDS; no vendor FFT library.
+// zero-padded FFT convolution with the free-space Green's function (Hockney's
+// method), the centred-difference field taken in the spectrum.  Each axis is
+// padded to the power of two mx >= 2 nx (my >= 2 ny): any such length makes
+// the cyclic convolution equal the linear one on nodes -1..n.  Hand-written
+// radix-4/2 Stockham FFTs in LDS; no vendor FFT library.
 //
-// Data flow for a charge grid q (nx x ny, rows i along x):
+// Data flow for a charge grid q (nx x ny, rows i along x; hy = my / 2):
 //   k_rows_fwd   one workgroup per row i: sum the row's partials exactly
 //                (uint64, + carries) or read a dense int64 row, scale to
-//                rho; the real row zero-padded to my = 2 ny is transformed as
-//                a complex FFT of half length (even/odd samples packed) and
-//                untangled into the half spectrum l = 0..ny   -> A^T [ny+1][nx]
-//   k_cols       per column l: FFT along x (length mx = 2 nx, zero-padded),
+//                rho; the real row zero-padded to my is transformed as a
+//                complex FFT of half length hy (even/odd samples packed) and
+//                untangled into the half spectrum l = 0..hy   -> A^T [hy+1][nx]
+//   k_cols       per column l: FFT along x (length mx, zero-padded),
 //                multiply by the real Green's spectrum G^(k,l) (inverse-FFT
 //                normalisation folded in), then two inverse FFTs run by two
 //                waves at once: -i sin(2 pi k/mx)/dx * Phi (the x central
 //                difference) and Phi, scaled by -i sin(2 pi l/my)/dy (the y
-//                central difference); rows 0..nx-1 kept -> Bx, By [nx][ny+1]
+//                central difference); rows 0..nx-1 kept -> Bx, By [nx][hy+1]
 //   k_rows_inv   per row i: both half spectra packed as Ex + i Ey, completed
 //                by Hermitian symmetry, one inverse FFT     -> ex, ey [nx][ny]
 // Taking the differences in the spectrum keeps the large constant part of
@@ -129,8 +131,8 @@ constexpr int kMaxPerThread = kMaxFft / 64;
 constexpr int kReduceChunk = 8;
 
 // Lane layout of a row reduction by NT threads: lanes = ny/4 16-byte chunks
-// cover one workgroup's row segment, and groups = NT/lanes groups of lanes
-// split the workgroups.
+// cover one workgroup's row segment (ny is a multiple of 4), and groups =
+// NT/lanes whole groups of lanes split the workgroups.
 struct RowLanes {
     int lanes, groups, grp, j0c;
 };
@@ -154,9 +156,11 @@ __device__ __forceinline__ unsigned long long reduce_row(const DepositTarget &de
 {
     const RowLanes L = row_lanes<NT>(ny, tid);
     const int groups = L.groups, grp = L.grp, j0c = L.j0c;
+    // when ny / 4 does not divide NT the last threads form no whole group
+    const bool member = grp < groups;
     unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
-    for (int b0 = grp; b0 < nblocks; b0 += groups * kReduceChunk) {
+    for (int b0 = member ? grp : nblocks; b0 < nblocks; b0 += groups * kReduceChunk) {
         uint4 v[kReduceChunk];
         int lo[kReduceChunk], hi[kReduceChunk];
         // Branch-free: every lane issues its loads back to back (a chunk
@@ -182,11 +186,13 @@ __device__ __forceinline__ unsigned long long reduce_row(const DepositTarget &de
             s3 += (j0c + 3 >= lo[u] && j0c + 3 <= hi[u]) ? v[u].w : 0u;
         }
     }
-    unsigned long long *mine = red + (size_t)grp * ny + j0c;
-    mine[0] = s0;
-    mine[1] = s1;
-    mine[2] = s2;
-    mine[3] = s3;
+    if (member) {
+        unsigned long long *mine = red + (size_t)grp * ny + j0c;
+        mine[0] = s0;
+        mine[1] = s1;
+        mine[2] = s2;
+        mine[3] = s3;
+    }
     __syncthreads();
     unsigned long long t = 0;
     if (tid < ny) {
@@ -220,16 +226,16 @@ __global__ void __launch_bounds__(kRowThreads)
 }
 
 // Row i of rho (from the partials when FROM_PARTIALS, else from a dense int64
-// grid), real and zero-padded to my: packed z[m] = rho[2m] + i rho[2m+1]
-// (m < ny/2; zero up to ny), Z = FFT_ny(z), then
-//   X[l] = (Z[l] + conj Z[ny-l]) / 2 - i W^l (Z[l] - conj Z[ny-l]) / 2,
-// W = exp(-2 pi i / my), for l = 0..ny.
-// LDS of the row-forward workgroup: twiddles [my], two FFT buffers [ny],
+// grid), real and zero-padded to my = 2 hy: packed z[m] = rho[2m] + i rho[2m+1]
+// (zero from index ny on), Z = FFT_hy(z), then
+//   X[l] = (Z[l] + conj Z[hy-l]) / 2 - i W^l (Z[l] - conj Z[hy-l]) / 2,
+// W = exp(-2 pi i / my), for l = 0..hy.
+// LDS of the row-forward workgroup: twiddles [my], two FFT buffers [hy],
 // rho [ny], then (16-byte aligned) the staged headers.
 template <typename T>
 __host__ __device__ constexpr size_t rows_fwd_hdr_offset(int ny, int my)
 {
-    return (sizeof(cx<T>) * (size_t)(my + 2 * ny) + sizeof(T) * (size_t)ny + 15) & ~(size_t)15;
+    return (sizeof(cx<T>) * (size_t)(2 * my) + sizeof(T) * (size_t)ny + 15) & ~(size_t)15;
 }
 
 template <typename T, bool FROM_PARTIALS, int NT>
@@ -240,10 +246,11 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
                                               int i, bool pipe)
 {
     extern __shared__ unsigned char smem_raw[];
+    const int half = my >> 1;                           // hy: complex FFT length
     cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // my entries
-    cx<T> *a = twl + my;                                // ny
-    cx<T> *b = a + ny;                                  // ny
-    T *rho = reinterpret_cast<T *>(b + ny);             // ny
+    cx<T> *a = twl + my;                                // hy
+    cx<T> *b = a + half;                                // hy
+    T *rho = reinterpret_cast<T *>(b + half);           // ny
     BlockHeader *hdr = reinterpret_cast<BlockHeader *>(smem_raw + rows_fwd_hdr_offset<T>(ny, my));
     __shared__ unsigned long long red[FROM_PARTIALS ? NT * 4 : 1];
     const int tid = threadIdx.x;
@@ -270,10 +277,9 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
         if (i == 0 || l == 0 || l == ny) return T(0);
         return l < ny ? rho[l] : -rho[my - l];
     };
-    const int half = ny;  // complex length: my / 2
     if (tid < half) a[tid] = cx<T>{sample(2 * tid), sample(2 * tid + 1)};
     const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, NT);
-    for (int l = tid; l <= ny; l += NT) {
+    for (int l = tid; l <= half; l += NT) {
         const cx<T> zl = Z[l & (half - 1)];
         const cx<T> zm = conj(Z[(half - l) & (half - 1)]);
         const cx<T> s = zl + zm, d = zl - zm;
@@ -370,15 +376,15 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
                                              false);
 }
 
-// Column l of the row spectra: forward FFT along x, times the Green's
-// spectrum, then the two differentiated inverse transforms, one per wave.
-// The second is the column-inverse of the potential's spectrum before the
-// y difference; bp, when not null, receives it as well for the node
-// potential, on rows -1..nx (row i at bp[(i + 1) * (ny + 1)]; row -1 is the
+// Column l (of hy + 1) of the row spectra: forward FFT along x, times the
+// Green's spectrum, then the two differentiated inverse transforms, one per
+// wave.  The second is the column-inverse of the potential's spectrum before
+// the y difference; bp, when not null, receives it as well for the node
+// potential, on rows -1..nx (row i at bp[(i + 1) * (hy + 1)]; row -1 is the
 // periodic row mx - 1, which the zero padding or the odd extension makes the
 // potential's value one node outside the grid).
 template <typename T>
-__device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, int ny, int mx,
+__device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, int hy, int mx,
                                           int log2mx, const cx<T> *__restrict__ tw,
                                           const T *__restrict__ ghat_t, const T *__restrict__ sx,
                                           const T *__restrict__ sy, cx<T> *__restrict__ bx,
@@ -439,37 +445,38 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     // past every butterfly, so they only keep the barriers
     const cx<T> *res = fft_lds(in, tmp, mx, log2mx, twl, 1, wave < 2 ? lane : mx, 64);
     if (wave == 0) {
-        for (int i = lane; i < nx; i += 64) bx[(size_t)i * (ny + 1) + l] = conj(res[i]);
+        for (int i = lane; i < nx; i += 64) bx[(size_t)i * (hy + 1) + l] = conj(res[i]);
     } else if (wave == 1) {
         for (int i = lane; i < nx; i += 64)
-            by[(size_t)i * (ny + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
+            by[(size_t)i * (hy + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
         if (bp)
             for (int i = lane - 1; i <= nx; i += 64)
-                bp[(size_t)(i + 1) * (ny + 1) + l] = conj(res[i < 0 ? mx - 1 : i]);
+                bp[(size_t)(i + 1) * (hy + 1) + l] = conj(res[i < 0 ? mx - 1 : i]);
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kColThreads)
-    k_cols(const cx<T> *__restrict__ at, int nx, int ny, int mx, int log2mx,
+    k_cols(const cx<T> *__restrict__ at, int nx, int hy, int mx, int log2mx,
            const cx<T> *__restrict__ tw, const T *__restrict__ ghat_t, const T *__restrict__ sx,
            const T *__restrict__ sy, cx<T> *__restrict__ bx, cx<T> *__restrict__ by, bool pipe,
            cx<T> *__restrict__ bp)
 {
-    cols_body<T>(at, nx, ny, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x, pipe, bp);
+    cols_body<T>(at, nx, hy, mx, log2mx, tw, ghat_t, sx, sy, bx, by, (int)blockIdx.x, pipe, bp);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
 {
     const BatchInstance &I = b.inst[b.col_inst[blockIdx.x]];
-    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.ny, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
+    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.my >> 1, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
                  (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
                  (cx<T> *)I.spec_by, (int)blockIdx.x - I.col_block0, false);
 }
 
-// Row i: Z[l] = Bx[l] + i By[l] for l = 0..ny and Z[my-l] = conj(Bx[l]) +
-// i conj(By[l]) for 0 < l < ny; one inverse FFT gives ex + i ey.  Written
+// Row i: Z[l] = Bx[l] + i By[l] for l = 0..hy and Z[my-l] = conj(Bx[l]) +
+// i conj(By[l]) for 0 < l < hy (hy = my / 2); one inverse FFT gives ex + i ey
+// on the first ny entries.  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
 // With bp (the potential's column-inverse spectrum), a second inverse FFT of
 // its Hermitian row writes row i of the node potential phi on columns
@@ -489,10 +496,11 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
     cx<T> *a = twl + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
+    const int hy = my >> 1;
     // rows -1 and nx have no field: their (unused) spectrum loads read row 0
     const int fi = (i >= 0 && i < nx) ? i : 0;
-    const cx<T> *rx = bx + (size_t)fi * (ny + 1);
-    const cx<T> *ry = by + (size_t)fi * (ny + 1);
+    const cx<T> *rx = bx + (size_t)fi * (hy + 1);
+    const cx<T> *ry = by + (size_t)fi * (hy + 1);
     constexpr int kPerT = kMaxFft / kInvThreads;          // twiddles per thread
     constexpr int kPerL = kMaxFft / 2 / kInvThreads + 1;  // spectrum entries per thread
     cx<T> vt[kPerT], vx[kPerL], vy[kPerL];
@@ -504,8 +512,8 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
 #pragma unroll
     for (int r = 0; r < kPerL; ++r) {
         const int l = tid + r * kInvThreads;
-        vx[r] = l <= ny ? rx[l] : cx<T>{T(0), T(0)};
-        vy[r] = l <= ny ? ry[l] : cx<T>{T(0), T(0)};
+        vx[r] = l <= hy ? rx[l] : cx<T>{T(0), T(0)};
+        vy[r] = l <= hy ? ry[l] : cx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int r = 0; r < kPerT; ++r) {
@@ -515,11 +523,11 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
 #pragma unroll
     for (int r = 0; r < kPerL; ++r) {
         const int l = tid + r * kInvThreads;
-        if (l <= ny) {
+        if (l <= hy) {
             const cx<T> X = vx[r], Y = vy[r];
             // conjugated inputs for conj(FFT(conj(.)))
             a[l] = conj(X + mul_pos_i(Y));
-            if (l > 0 && l < ny) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
+            if (l > 0 && l < hy) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
         }
     }
     const bool field_row = i >= 0 && i < nx;
@@ -538,11 +546,11 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
     if (bp) {
         cx<T> *a2 = b + my;
         cx<T> *b2 = a2 + my;
-        const cx<T> *rp = bp + (size_t)(i + 1) * (ny + 1);
-        for (int l = tid; l <= ny; l += kInvThreads) {
+        const cx<T> *rp = bp + (size_t)(i + 1) * (hy + 1);
+        for (int l = tid; l <= hy; l += kInvThreads) {
             const cx<T> P = rp[l];
             a2[l] = conj(P);
-            if (l > 0 && l < ny) a2[my - l] = P;
+            if (l > 0 && l < hy) a2[my - l] = P;
         }
         const cx<T> *r2 = fft_lds(a2, b2, my, log2my, twl, 1, tid, kInvThreads);
         T *row = phi + (size_t)(i + 1) * (ny + 2);
@@ -578,8 +586,8 @@ hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *e
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)w.mx;
     const size_t inv_lds = (want_phi ? 5 : 3) * sizeof(cx<T>) * (size_t)w.my;
     cx<T> *bp = want_phi ? (cx<T> *)w.spec_p : nullptr;
-    hipLaunchKernelGGL(k_cols<T>, dim3(w.ny + 1), dim3(kColThreads), col_lds, s,
-                       (const cx<T> *)w.spec_a, w.nx, w.ny, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
+    hipLaunchKernelGGL(k_cols<T>, dim3(w.my / 2 + 1), dim3(kColThreads), col_lds, s,
+                       (const cx<T> *)w.spec_a, w.nx, w.my / 2, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
                        (const T *)w.ghat_t, (const T *)w.sx, (const T *)w.sy, (cx<T> *)w.spec_bx,
                        (cx<T> *)w.spec_by, w.pipe, bp);
     hipError_t e = hipGetLastError();
@@ -611,9 +619,9 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
 
 template <typename T>
 hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows, int cols,
-                                  int max_nx, int max_ny, int max_pass_blocks)
+                                  int max_mx, int max_ny, int max_my, int max_pass_blocks)
 {
-    const int mmx = 2 * max_nx, mmy = 2 * max_ny;
+    const int mmx = max_mx, mmy = max_my;
     const size_t row_lds = rows_fwd_hdr_offset<T>(max_ny, mmy) +
                            sizeof(BlockHeader) * (size_t)std::max(max_pass_blocks, 1);
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
@@ -631,10 +639,11 @@ hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows,
 }  // namespace
 
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny, int max_pass_blocks)
+                                int cols, int max_mx, int max_ny, int max_my, int max_pass_blocks)
 {
-    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_nx, max_ny, max_pass_blocks)
-                 : launch_solve_batched_t<double>(s, b, rows, cols, max_nx, max_ny,
+    return mixed ? launch_solve_batched_t<float>(s, b, rows, cols, max_mx, max_ny, max_my,
+                                                 max_pass_blocks)
+                 : launch_solve_batched_t<double>(s, b, rows, cols, max_mx, max_ny, max_my,
                                                   max_pass_blocks);
 }
 

@@ -37,14 +37,19 @@ scpic_status fail_hip(hipError_t e, const char *what)
         if (e_ != hipSuccess) return fail_hip(e_, what); \
     } while (0)
 
-bool is_pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
-
 int ilog2(int v)
 {
     int r = 0;
     while ((1 << r) < v) ++r;
     return r;
 }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// FFT length of an axis of n nodes: the smallest power of two >= 2 n.  The
+// open-boundary kernel sampled at min(k, m - k) then makes the cyclic
+// convolution equal the linear one on nodes -1..n for any such m.
+int fft_len(int n) { return 1 << ilog2(2 * n); }
 
 // One launch of the particle pass, as scheduled by scpic_track.
 struct PassOp {
@@ -127,7 +132,7 @@ scpic_status ensure_potential(scpic_ctx *c)
     void *phi = nullptr, *spec = nullptr;
     if (scpic_status st = dev_alloc(c, &phi, es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 2)))
         return st;
-    if (scpic_status st = dev_alloc(c, &spec, 2 * es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 1)))
+    if (scpic_status st = dev_alloc(c, &spec, 2 * es * (size_t)(c->grid.nx + 2) * (c->sw.my / 2 + 1)))
         return st;
     SCPIC_HIP_TRY(hipMemset(phi, 0, es * (size_t)(c->grid.nx + 2) * (c->grid.ny + 2)), "hipMemset");
     c->sw.phi = phi;
@@ -165,8 +170,8 @@ scpic_status check_grid(const scpic_grid *grid)
     if (!(grid->dx > 0.0) || !(grid->dy > 0.0) || !std::isfinite(grid->dx) ||
         !std::isfinite(grid->dy) || !std::isfinite(grid->x_min) || !std::isfinite(grid->y_min))
         return fail(SCPIC_EINVAL, "grid spacing must be positive and finite, origin finite");
-    if (!is_pow2_in(grid->nx, 8, 256) || !is_pow2_in(grid->ny, 8, 256))
-        return fail(SCPIC_EUNSUPPORTED, "nx and ny must be powers of two in [8, 256]");
+    if (grid->nx < 8 || grid->nx > 256 || grid->ny < 8 || grid->ny > 256 || grid->ny % 4 != 0)
+        return fail(SCPIC_EUNSUPPORTED, "nx must be in [8, 256] and ny a multiple of 4 in [8, 256]");
     if ((int64_t)grid->nx * grid->ny > kMaxCells)
         return fail(SCPIC_EUNSUPPORTED, "nx * ny must not exceed 65536");
     return SCPIC_OK;
@@ -508,13 +513,14 @@ double green_offset(int di, int dj, double dx, double dy)
 
 namespace scpic {
 
-// Spectrum of the 2nx x 2ny periodic kernel Gp(X, Y) = G(min(X, mx-X),
-// min(Y, my-Y)).  Gp is even in both offsets, so its DFT is the real cosine
-// sum; it is taken separably (over Y, then X) and divided by mx*my, the
-// normalisation of the unnormalised inverse transforms.  Layout [ny+1][mx].
-void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t)
+// Spectrum of the mx x my periodic kernel Gp(X, Y) = G(min(X, mx-X),
+// min(Y, my-Y)) (mx >= 2 nx, my >= 2 ny).  Gp is even in both offsets, so its
+// DFT is the real cosine sum; it is taken separably (over Y, then X) and
+// divided by mx*my, the normalisation of the unnormalised inverse
+// transforms.  Layout [my/2+1][mx].
+void green_spectrum_host(int mx, int my, double dx, double dy, double *ghat_t)
 {
-    const int mx = 2 * nx, my = 2 * ny;
+    const int ny = my / 2;  // the half spectrum's last column
     std::vector<double> cxs(mx), cys(my), gp((size_t)mx * my), h((size_t)mx * (ny + 1));
     for (int t = 0; t < mx; ++t) cxs[t] = std::cos(2.0 * M_PI * t / mx);
     for (int t = 0; t < my; ++t) cys[t] = std::cos(2.0 * M_PI * t / my);
@@ -563,17 +569,19 @@ namespace {
 // Green's spectrum (open boundary) or the pipe's mode divisors, twiddles and
 // difference factors of a grid, converted to T and copied to the given
 // device tables.
+// The pipe needs mx = 2 nx and my = 2 ny (its walls sit at node 0 and node
+// n of each axis); the open boundary takes the padded lengths of fft_len.
 template <typename T>
 scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x, void *tw_y,
                                 void *sx_t, void *sy_t, bool pipe = false)
 {
-    const int nx = grid.nx, ny = grid.ny, mx = 2 * nx, my = 2 * ny;
-    std::vector<double> ghat((size_t)(ny + 1) * mx);
+    const int nx = grid.nx, ny = grid.ny, mx = fft_len(nx), my = fft_len(ny), hy = my / 2;
+    std::vector<double> ghat((size_t)(hy + 1) * mx);
     if (pipe)
         pipe_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
     else
-        green_spectrum_host(nx, ny, grid.dx, grid.dy, ghat.data());
-    std::vector<T> g_t(ghat.size()), twx(2 * (size_t)mx), twy(2 * (size_t)my), sx(mx), sy(ny + 1);
+        green_spectrum_host(mx, my, grid.dx, grid.dy, ghat.data());
+    std::vector<T> g_t(ghat.size()), twx(2 * (size_t)mx), twy(2 * (size_t)my), sx(mx), sy(hy + 1);
     for (size_t i = 0; i < ghat.size(); ++i) g_t[i] = (T)ghat[i];
     for (int t = 0; t < mx; ++t) {
         twx[2 * t] = (T)std::cos(2.0 * M_PI * t / mx);
@@ -584,7 +592,7 @@ scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x
         twy[2 * t] = (T)std::cos(2.0 * M_PI * t / my);
         twy[2 * t + 1] = (T)(-std::sin(2.0 * M_PI * t / my));
     }
-    for (int l = 0; l <= ny; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / grid.dy);
+    for (int l = 0; l <= hy; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / grid.dy);
     SCPIC_HIP_TRY(hipMemcpy(ghat_t, g_t.data(), sizeof(T) * g_t.size(), hipMemcpyHostToDevice), "upload ghat");
     SCPIC_HIP_TRY(hipMemcpy(tw_x, twx.data(), sizeof(T) * twx.size(), hipMemcpyHostToDevice), "upload twiddles");
     SCPIC_HIP_TRY(hipMemcpy(tw_y, twy.data(), sizeof(T) * twy.size(), hipMemcpyHostToDevice), "upload twiddles");
@@ -634,20 +642,21 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     c->dep.max_blocks = c->max_blocks;
     c->sw.nx = nx;
     c->sw.ny = ny;
-    c->sw.mx = 2 * nx;
-    c->sw.my = 2 * ny;
-    c->sw.log2_mx = ilog2(2 * nx);
-    c->sw.log2_my = ilog2(2 * ny);
+    const int mx = fft_len(nx), my = fft_len(ny), hy = my / 2;
+    c->sw.mx = mx;
+    c->sw.my = my;
+    c->sw.log2_mx = ilog2(mx);
+    c->sw.log2_my = ilog2(my);
     c->sw.mixed = c->mixed;
     c->sw.pipe = false;
-    ALLOC(c->sw.tw_x, ce * 2 * nx);
-    ALLOC(c->sw.tw_y, ce * 2 * ny);
-    ALLOC(c->sw.ghat_t, fe * (size_t)(ny + 1) * 2 * nx);
-    ALLOC(c->sw.sx, fe * 2 * nx);
-    ALLOC(c->sw.sy, fe * (ny + 1));
-    ALLOC(c->sw.spec_a, ce * (size_t)(ny + 1) * nx);
-    ALLOC(c->sw.spec_bx, ce * (size_t)(ny + 1) * nx);
-    ALLOC(c->sw.spec_by, ce * (size_t)(ny + 1) * nx);
+    ALLOC(c->sw.tw_x, ce * mx);
+    ALLOC(c->sw.tw_y, ce * my);
+    ALLOC(c->sw.ghat_t, fe * (size_t)(hy + 1) * mx);
+    ALLOC(c->sw.sx, fe * mx);
+    ALLOC(c->sw.sy, fe * (hy + 1));
+    ALLOC(c->sw.spec_a, ce * (size_t)(hy + 1) * nx);
+    ALLOC(c->sw.spec_bx, ce * (size_t)(hy + 1) * nx);
+    ALLOC(c->sw.spec_by, ce * (size_t)(hy + 1) * nx);
     ALLOC(c->ef, 2 * fe * ncell);
     ALLOC(c->diag_part, sizeof(double) * kMomentBlocks * kMoments);
     ALLOC(c->diag_sums, sizeof(double) * 2 * kMoments);
@@ -731,6 +740,9 @@ scpic_status scpic_set_option(scpic_ctx *ctx, int32_t option, int64_t value)
             return fail(SCPIC_EINVAL, "solver must be SCPIC_SOLVER_OPEN or SCPIC_SOLVER_PIPE");
         const bool pipe = value == SCPIC_SOLVER_PIPE;
         if (pipe == ctx->sw.pipe) return SCPIC_OK;
+        if (pipe && !(is_pow2(ctx->grid.nx) && is_pow2(ctx->grid.ny)))
+            return fail(SCPIC_EUNSUPPORTED, "the grounded pipe needs nx and ny powers of two (its "
+                                            "odd extension has length 2n, a radix-2/4 FFT length)");
         // captured turns carry the solver: drop them once queued work is done
         SCPIC_HIP_TRY(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
         for (auto &g : ctx->graphs)
@@ -1065,7 +1077,7 @@ struct scpic_batch {
     std::vector<scpic_grid> grids;
     std::vector<BatchInstance> inst;  // host copy of the device table
     BatchLaunch launch{};
-    int total_pass_blocks = 0, total_rows = 0, total_cols = 0, max_nx = 0, max_ny = 0;
+    int total_pass_blocks = 0, total_rows = 0, total_cols = 0, max_mx = 0, max_ny = 0, max_my = 0;
     int max_beam_blocks = 0;  // most pass workgroups of one beam in the current layout
     std::vector<void *> allocations;
     std::vector<BatchSchedule> schedules;
@@ -1231,11 +1243,12 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         I.row_block0 = b->total_rows;
         b->total_rows += nx;
         I.col_block0 = b->total_cols;
-        b->total_cols += ny + 1;
-        b->max_nx = std::max(b->max_nx, nx);
+        b->total_cols += fft_len(ny) / 2 + 1;
+        b->max_mx = std::max(b->max_mx, fft_len(nx));
         b->max_ny = std::max(b->max_ny, ny);
+        b->max_my = std::max(b->max_my, fft_len(ny));
         for (int t = 0; t < nx; ++t) row_inst.push_back((uint16_t)k);
-        for (int t = 0; t <= ny; ++t) col_inst.push_back((uint16_t)k);
+        for (int t = 0; t <= fft_len(ny) / 2; ++t) col_inst.push_back((uint16_t)k);
         I.g.nx = nx;
         I.g.ny = ny;
         I.g.x_min = gr.x_min;
@@ -1249,10 +1262,10 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         I.dep.max_blocks = slices;
         I.nx = nx;
         I.ny = ny;
-        I.mx = 2 * nx;
-        I.my = 2 * ny;
-        I.log2_mx = ilog2(2 * nx);
-        I.log2_my = ilog2(2 * ny);
+        I.mx = fft_len(nx);
+        I.my = fft_len(ny);
+        I.log2_mx = ilog2(I.mx);
+        I.log2_my = ilog2(I.my);
         I.scale = n_k > 0 ? 1.0 / (kChargeOne * (double)n_k) : 0.0;
         const GridTables *gt = nullptr;
         for (const GridTables &t : tables)
@@ -1261,11 +1274,11 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         if (!gt) {
             GridTables t;
             t.grid = gr;
-            BALLOC(t.tw_x, ce * 2 * nx);
-            BALLOC(t.tw_y, ce * 2 * ny);
-            BALLOC(t.ghat_t, fe * (size_t)(ny + 1) * 2 * nx);
-            BALLOC(t.sx, fe * 2 * nx);
-            BALLOC(t.sy, fe * (ny + 1));
+            BALLOC(t.tw_x, ce * I.mx);
+            BALLOC(t.tw_y, ce * I.my);
+            BALLOC(t.ghat_t, fe * (size_t)(I.my / 2 + 1) * I.mx);
+            BALLOC(t.sx, fe * I.mx);
+            BALLOC(t.sy, fe * (I.my / 2 + 1));
             st = b->mixed ? upload_grid_tables<float>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy)
                           : upload_grid_tables<double>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy);
             if (st) return st;
@@ -1277,9 +1290,9 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         I.ghat_t = gt->ghat_t;
         I.sx = gt->sx;
         I.sy = gt->sy;
-        BALLOC(I.spec_a, ce * (size_t)(ny + 1) * nx);
-        BALLOC(I.spec_bx, ce * (size_t)(ny + 1) * nx);
-        BALLOC(I.spec_by, ce * (size_t)(ny + 1) * nx);
+        BALLOC(I.spec_a, ce * (size_t)(I.my / 2 + 1) * nx);
+        BALLOC(I.spec_bx, ce * (size_t)(I.my / 2 + 1) * nx);
+        BALLOC(I.spec_by, ce * (size_t)(I.my / 2 + 1) * nx);
         BALLOC(I.ef, 2 * fe * ncell);
         SCPIC_HIP_TRY(hipMemset(I.dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
         SCPIC_HIP_TRY(hipMemset(I.dep.header, 0xff, sizeof(BlockHeader) * slices), "hipMemset");
@@ -1390,7 +1403,7 @@ scpic_status batch_enqueue(scpic_batch *b, hipStream_t s, const scpic_particles 
         if (e != hipSuccess) return fail_hip(e, "batched pass launch");
         if (op.deposit) {
             e = launch_solve_batched(s, b->launch, b->mixed, b->total_rows, b->total_cols,
-                                     b->max_nx, b->max_ny, b->max_beam_blocks);
+                                     b->max_mx, b->max_ny, b->max_my, b->max_beam_blocks);
             if (e != hipSuccess) return fail_hip(e, "batched solve launch");
         }
     }

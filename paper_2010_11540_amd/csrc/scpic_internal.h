@@ -27,7 +27,8 @@ constexpr int kPassStaticLds = 2048;
 // Most split steps a thick sextupole may take.
 constexpr int kMaxSextSteps = 1024;
 
-// Largest FFT length (2 * largest grid side) and largest grid.
+// Largest FFT length (the padded length of the largest grid side, 256) and
+// largest grid.
 constexpr int kMaxFft = 512;
 constexpr int kMaxCells = 65536;
 
@@ -130,7 +131,7 @@ struct BatchLaunch {
     const BatchInstance *inst;
     const uint16_t *pass_inst;  // [total pass workgroups]
     const uint16_t *row_inst;   // [sum nx]: row-forward and row-inverse kernels
-    const uint16_t *col_inst;   // [sum (ny + 1)]: column kernel
+    const uint16_t *col_inst;   // [sum (my/2 + 1)]: column kernel
     int32_t n_inst;
 };
 
@@ -176,16 +177,16 @@ hipError_t launch_reduce(hipStream_t s, const DepositTarget &dep, int blocks_use
 
 // ---- launchers (fft_solve.hip) -------------------------------------------
 struct SolveWorkspace {
-    int nx, ny, mx, my, log2_mx, log2_my;
+    int nx, ny, mx, my, log2_mx, log2_my;  // mx, my: FFT lengths, powers of two >= 2n
     bool mixed;
     bool pipe;           // grounded rectangular pipe instead of the open boundary
     void *tw_x, *tw_y;   // [mx], [my] complex twiddles exp(-2 pi i t / m)
-    void *ghat_t;        // [ny+1][mx] real Green's spectrum / (mx my), transposed
-    void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [ny+1] sin(2 pi l / my)/dy
-    void *spec_a;        // [ny+1][nx] complex, rows transformed
-    void *spec_bx, *spec_by;  // [nx][ny+1] complex, after the column pass
+    void *ghat_t;        // [my/2+1][mx] real Green's spectrum / (mx my), transposed
+    void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [my/2+1] sin(2 pi l / my)/dy
+    void *spec_a;        // [my/2+1][nx] complex, rows transformed
+    void *spec_bx, *spec_by;  // [nx][my/2+1] complex, after the column pass
     // node potential (want_phi; for the line density or the B-spline gather):
-    // the potential's column-inverse spectrum [nx+2][ny+1] complex (rows
+    // the potential's column-inverse spectrum [nx+2][my/2+1] complex (rows
     // -1..nx) and the potential on nodes -1..nx by -1..ny [(nx+2)*(ny+2)];
     // with line.nz > 0 the line tables reduced from the pass's histograms
     bool want_phi = false;
@@ -205,14 +206,15 @@ hipError_t launch_solve_partials(hipStream_t s, const SolveWorkspace &w, const D
                                  int blocks_used, double scale, void *ef);
 
 // Field of every beam of a batch from the partials of its last batched pass,
-// interleaved into each beam's ef: rows = sum of nx, cols = sum of (ny + 1);
-// max_pass_blocks bounds every beam's pass workgroups.
+// interleaved into each beam's ef: rows = sum of nx, cols = sum of (my/2 + 1);
+// max_mx, max_ny, max_my bound every beam's (padded) lengths and
+// max_pass_blocks every beam's pass workgroups.
 hipError_t launch_solve_batched(hipStream_t s, const BatchLaunch &b, bool mixed, int rows,
-                                int cols, int max_nx, int max_ny, int max_pass_blocks);
+                                int cols, int max_mx, int max_ny, int max_my, int max_pass_blocks);
 
-// Green's spectrum helper on the host (api.hip): fills ghat_t (FP64) for
-// the padded 2nx x 2ny periodic kernel.
-void green_spectrum_host(int nx, int ny, double dx, double dy, double *ghat_t);
+// Green's spectrum helper on the host (api.hip): fills ghat_t (FP64,
+// [my/2+1][mx]) for the mx x my periodic kernel (mx >= 2 nx, my >= 2 ny).
+void green_spectrum_host(int mx, int my, double dx, double dy, double *ghat_t);
 
 // The grounded pipe's counterpart of ghat_t (same layout and normalisation):
 // the inverse of the 5-point Laplacian's eigenvalue per mode of the odd

@@ -54,7 +54,8 @@ def _grid(nx=64, ny=64, dx=1e-4, dy=1e-4):
     return Grid(nx, ny, -3e-3, -3e-3, dx, dy)
 
 
-@pytest.mark.parametrize("kw,code", [({"nx": 100}, -4), ({"ny": 512}, -4), ({"nx": 4}, -4),
+@pytest.mark.parametrize("kw,code", [({"ny": 102}, -4), ({"ny": 512}, -4), ({"nx": 4}, -4),
+                                     ({"nx": 257}, -4), ({"ny": 260}, -4), ({"ny": 4}, -4),
                                      ({"dx": 0.0}, -1), ({"dy": -1e-4}, -1),
                                      ({"dx": float("nan")}, -1), ({"nx": 512, "ny": 256}, -4)])
 def test_create_rejects_bad_grids_before_touching_the_device(lib, kw, code):
@@ -97,7 +98,7 @@ def test_batch_create_rejects_bad_arguments_before_touching_the_device(lib):
     from paper_2010_11540_amd.scpic import Grid
     h = ctypes.c_void_p(123)
     good = (Grid * 2)(_grid(), _grid(32, 32))
-    bad_grid = (Grid * 2)(_grid(), _grid(nx=100))
+    bad_grid = (Grid * 2)(_grid(), _grid(ny=98))
     off = lambda *v: (ctypes.c_int64 * len(v))(*v)
     cases = [
         (good, off(0, 10, 20), 0, 0, -1),     # n_inst 0

@@ -45,19 +45,22 @@ def _turn_err(h, ref):
 
 
 def _mixed_batch():
-    """Five beams: different sizes (one empty, one below a workgroup), grids
-    (square, anisotropic, rectangular), tunes and element kinds, one shared
-    schedule of 16 SC locations per turn."""
+    """Six beams: different sizes (one empty, one below a workgroup), grids
+    (square, anisotropic, rectangular, and 100 x 36 whose sides are not
+    powers of two), tunes and element kinds, one shared schedule of 16 SC
+    locations per turn."""
     eps = 1e-6
     kappa = inputs.kappa_for_tune_shift(-0.2, eps, 16)
-    sizes = [3000, 0, 12001, 700, 20000]
+    sizes = [3000, 0, 12001, 700, 20000, 9001]
     grids = [inputs.make_grid(32), inputs.make_grid(64), inputs.make_grid(64, 64, 5e-3, 7e-3),
-             inputs.make_grid(16, 32, 6e-3, 6e-3), inputs.make_grid(64)]
+             inputs.make_grid(16, 32, 6e-3, 6e-3), inputs.make_grid(64),
+             inputs.make_grid(100, 36, 6e-3, 5e-3)]
     lattices = [inputs.ring(4.2, 4.3, 16, kappa),
                 inputs.ring(4.1, 4.2, 16, kappa),
                 inputs.ring(4.31, 4.17, 16, 2 * kappa, four_by_four=True, k2l=5.0, sext_every=4),
                 inputs.ring(4.05, 4.08, 16, kappa),
-                inputs.ring(4.45, 4.25, 16, kappa, four_by_four=True)]
+                inputs.ring(4.45, 4.25, 16, kappa, four_by_four=True),
+                inputs.ring(4.22, 4.33, 16, kappa)]
     beams = [inputs.gaussian_beam(n, 500 + k) for k, n in enumerate(sizes)]
     parts, offsets = inputs.concat_parts(beams)
     return parts, offsets, grids, lattices
@@ -65,7 +68,7 @@ def _mixed_batch():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_equals_single_beam_path(gpu, precision):
-    _say(f"batch of 5 beams, 3 turns, {precision}: batched == single-beam, bit-exact")
+    _say(f"batch of 6 beams, 3 turns, {precision}: batched == single-beam, bit-exact")
     parts, offsets, grids, lattices = _mixed_batch()
     with gpu.Batch(grids, offsets, precision) as b:
         d = _dev(parts)
@@ -90,7 +93,7 @@ def test_batch_equals_single_beam_path(gpu, precision):
 
 
 def test_batch_one_turn_matches_oracle(gpu, orc):
-    _say("batch of 5 beams, 1 turn fp64 vs oracle")
+    _say("batch of 6 beams, 1 turn fp64 vs oracle")
     parts, offsets, grids, lattices = _mixed_batch()
     with gpu.Batch(grids, offsets) as b:
         d = _dev(parts)

@@ -42,7 +42,9 @@ def _field_err(got, want):
 
 @pytest.mark.parametrize("n,nx,ny,seed", [(10_000, 64, 64, 1), (1, 64, 64, 2), (63, 32, 16, 3),
                                           (100_003, 128, 128, 4), (0, 64, 64, 5),
-                                          (1_000_000, 128, 128, 6), (257_000, 64, 128, 7)])
+                                          (1_000_000, 128, 128, 6), (257_000, 64, 128, 7),
+                                          (100_000, 100, 100, 21), (257_003, 96, 64, 22),
+                                          (50_001, 37, 100, 23), (1_000_000, 100, 100, 24)])
 def test_deposit_bit_exact(gpu, orc, n, nx, ny, seed):
     _say(f"deposit n={n} grid={nx}x{ny} seed={seed}")
     g = inputs.make_grid(nx, ny, 4.5e-3, 5e-3)
@@ -160,7 +162,12 @@ def _charge(n, seed, g, orc):
 @pytest.mark.parametrize("nx,ny,hx,hy", [(64, 64, 6e-3, 6e-3), (128, 128, 6e-3, 6e-3),
                                          (64, 32, 6e-3, 4e-3), (16, 128, 5e-3, 7e-3),
                                          (8, 8, 6e-3, 6e-3), (256, 256, 12e-3, 6e-3),
-                                         (256, 32, 8e-3, 3e-3)])
+                                         (256, 32, 8e-3, 3e-3),
+                                         # not powers of two: padded to the next power
+                                         # of two of at least twice the side
+                                         (100, 100, 6e-3, 6e-3), (96, 64, 6e-3, 4e-3),
+                                         (37, 100, 3e-3, 7e-3), (200, 36, 8e-3, 3e-3),
+                                         (9, 12, 2e-3, 2e-3)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
 def test_solve_matches_oracle(gpu, orc, nx, ny, hx, hy, precision, tol):
     _say(f"solve {precision} grid={nx}x{ny}")
@@ -193,6 +200,44 @@ def test_pipe_solve_matches_oracle(gpu, orc, nx, ny, hx, hy, precision, tol):
         ey = ey.double().cpu().numpy()
     assert _field_err(ex, ex_ref) <= tol, _field_err(ex, ex_ref)
     assert _field_err(ey, ey_ref) <= tol, _field_err(ey, ey_ref)
+
+
+def test_pipe_needs_power_of_two_sides(gpu):
+    _say("pipe rejects a 100 x 100 grid")
+    g = inputs.make_grid(100, 100, 6e-3, 6e-3)
+    with gpu.Context(g) as ctx:
+        with pytest.raises(gpu.ScpicError) as e:
+            ctx.set_option(gpu.OPT_SOLVER, gpu.SOLVER_PIPE)
+        assert e.value.code == -4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_turn_on_the_papers_100_grid(gpu, orc, precision):
+    """The small ring on a 100 x 100 grid over +-6 sigma (the paper's grid
+    size): one turn of 16 SC steps, graph on, against the oracle."""
+    _say(f"track 100x100 grid 1 turn {precision}")
+    g = inputs.make_grid(100)
+    p = inputs.gaussian_beam(20_011, 31)
+    lat = inputs.ring(4.2, 4.3, 16, inputs.kappa_for_tune_shift(-0.2, 1e-6, 16))
+    ref = inputs.copy_parts(p)
+    orc.track(ref, g, lat, 1)
+    with gpu.Context(g, precision) as ctx:
+        d = _dev(p)
+        ctx.track(d, lat, 1)
+        h = _host(d)
+    np.testing.assert_array_equal(h["lost"], ref["lost"])
+    err = _turn_err(h, ref)
+    bar = 1e-10
+    if precision == "mixed":
+        # each of the 16 kicks carries at most the FP32 field bar (1e-5 of
+        # max|E|) times kappa, relative to the rms momenta, doubled
+        q, _ = orc.deposit(inputs.copy_parts(p), g)
+        ex0, ey0 = orc.solve(q, 1.0 / ((1 << 24) * len(p["x"])), g)
+        kappa = float(lat["p"][lat["kind"] == inputs.SC][0, 0])
+        emax = max(np.abs(ex0).max(), np.abs(ey0).max())
+        bar = 2 * 16 * 1e-5 * kappa * emax / min(ref["px"].std(), ref["py"].std())
+    print(f"[result] 100x100 one turn {precision}: {err:.3e} (bar {bar:.3e})", flush=True)
+    assert err <= bar, (err, bar)
 
 
 def test_solve_zero_charge_gives_zero_field(gpu):

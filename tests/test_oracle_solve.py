@@ -70,6 +70,20 @@ def test_round_gaussian_field_closed_form_second_order(orc):
     assert t128 < 5e-4
 
 
+def test_round_gaussian_field_on_a_100_node_grid(orc):
+    """The paper's grid size (100 x 100, not a power of two): the round
+    Gaussian's closed-form E_r within the second-order error the 64 and 128
+    grids bracket."""
+    e64, _ = _gaussian_field_error(orc, 64)
+    e100, t100 = _gaussian_field_error(orc, 100)
+    e128, _ = _gaussian_field_error(orc, 128)
+    assert e128 < e100 < e64
+    # second order: the error scales with (dx_64 / dx_100)^2 within 15 %
+    ratio = e64 / e100
+    assert abs(ratio / ((99 / 63) ** 2) - 1) < 0.15, ratio
+    assert t100 < 1e-3
+
+
 def test_uniform_ellipse_field_is_linear_inside_on_anisotropic_grid(orc):
     """Uniform ellipse (a, b): E_x = 2x/(a(a+b)), E_y = 2y/(b(a+b)) inside; the
     grid has dx != dy and nx != ny so that any swapped axis shows."""
