@@ -66,3 +66,19 @@ def laslett_tune_shift(n_ppb, harmonic, r_p, beta0, gamma0, eps_1sigma, bunch_fa
     """Incoherent tune spread estimate of a Gaussian bunch (Sec. V)."""
     return -n_ppb * harmonic * r_p / (4 * math.pi * beta0 ** 2 * gamma0 ** 3 * eps_1sigma
                                       * bunch_factor)
+
+
+def record_figures(name: str, figures: dict) -> None:
+    """Keep a test's printed figures: merged into gpurun_out/test_figures.json
+    at the repository root (one entry per name, overwritten by a rerun)."""
+    import json
+    from pathlib import Path
+
+    out = Path(__file__).resolve().parent.parent / "gpurun_out" / "test_figures.json"
+    out.parent.mkdir(exist_ok=True)
+    try:
+        data = json.loads(out.read_text())
+    except (OSError, ValueError):
+        data = {}
+    data[name] = figures
+    out.write_text(json.dumps(data, indent=1, sort_keys=True))
