@@ -420,6 +420,36 @@ scpic_status scpic_batch_autotune(scpic_batch *b, const scpic_particles *parts,
  * each, double or float per precision). */
 scpic_status scpic_batch_get_field(scpic_batch *b, int32_t k, void *ex, void *ey);
 
+/* ---- deposit without allocation ----------------------------------------
+ * For callers that cannot allocate device memory: code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * cloud-in-cell deposit as scpic_deposit (same weights, same exact integer
+ * result, which does not depend on the launch shape) without a context: its
+ * per-workgroup charge partials, their headers and the carry grid live in a
+ * static device array of the library, SCPIC_STATIC_SCRATCH_BYTES per device,
+ * held by every device the library runs on until the process ends.  Nothing
+ * is allocated: no hipMalloc or hipFree, no memset nodes (the scratch it needs
+ * cleared is cleared by a kernel at the start of each call), so the call can
+ * be captured.  The first call on a device looks up the array's address on
+ * that device and sets the pass kernels' LDS limit (both outside any capture
+ * on that device: make one uncaptured call first).
+ * grid: host, the limits of scpic_create.  parts: as scpic_deposit (lost may
+ * be NULL; out-of-domain particles are marked lost when it is not).
+ * rho: device, nx*ny int64, overwritten.  n_in: device, one int64, may be
+ * NULL.  hip_stream: the stream to enqueue on (NULL = the null stream).
+ * Every call on one device shares that device's array and leaves its own
+ * contents in it: calls that overlap on one device (on different streams, or
+ * from different host threads) race and must be serialised by the caller.
+ * Errors, before anything is enqueued: SCPIC_EINVAL (NULL grid, particles or
+ * rho; bad particle arrays or grid spacing), SCPIC_EUNSUPPORTED (grid beyond
+ * scpic_create's limits, or more than 64 * (2^31 - 1) particles); SCPIC_EHIP
+ * if the address lookup or a launch fails. */
+#define SCPIC_STATIC_SCRATCH_BYTES 17303552 /* 64 workgroups' partials of a
+                                               65536-node grid, their headers
+                                               and a 65536-node carry grid */
+scpic_status scpic_deposit_static(const scpic_grid *grid, const scpic_particles *parts,
+                                  int64_t *rho, int64_t *n_in, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

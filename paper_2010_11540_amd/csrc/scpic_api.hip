@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1690,6 +1691,126 @@ scpic_status scpic_batch_get_field(scpic_batch *b, int32_t k, void *ex, void *ey
     const BatchInstance &I = b->inst[k];
     hipError_t e = launch_interleave(b->stream, b->mixed, false, ex, ey, I.ef, I.nx * I.ny);
     if (e != hipSuccess) return fail_hip(e, "field copy launch");
+    return SCPIC_OK;
+}
+
+}  // extern "C"
+
+// ---- deposit without allocation ---------------------------------------------
+//
+// scpic_deposit_static runs the deposit of scpic_deposit (the same pass and
+// reduction kernels) with its per-workgroup partials, headers and carry grid
+// in one file-scope device array instead of a context's allocations.  The
+// array's host-side name is not a device address: host code uses only the
+// address hipGetSymbolAddress returns, looked up once per device.
+
+namespace {
+
+constexpr int kStaticBlocks = 64;  // workgroups of the allocation-free deposit
+constexpr size_t kStaticHeaderBytes = sizeof(BlockHeader) * kStaticBlocks;
+constexpr size_t kStaticCarryBytes = sizeof(unsigned long long) * kMaxCells;
+constexpr size_t kStaticPartialBytes = sizeof(uint32_t) * (size_t)kStaticBlocks * kMaxCells;
+constexpr size_t kStaticScratchBytes = kStaticHeaderBytes + kStaticCarryBytes + kStaticPartialBytes;
+static_assert(kStaticScratchBytes == SCPIC_STATIC_SCRATCH_BYTES,
+              "the header states the scratch size");
+static_assert(kStaticHeaderBytes % 256 == 0 && kStaticCarryBytes % 256 == 0,
+              "each part of the scratch starts 256-byte aligned");
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mutex;
+unsigned char *g_static_ptr[kMaxDevices] = {};
+bool g_static_ready[kMaxDevices] = {};
+
+// Headers to "unknown" (every word -1: the first tile is the whole grid when
+// it fits) and the carry grid's first ncell words to zero, by a kernel rather
+// than a memset node, so that the call can be captured into a graph.
+__global__ void __launch_bounds__(256)
+    k_static_clear(BlockHeader *__restrict__ header, unsigned long long *__restrict__ carry,
+                   int ncell)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kStaticBlocks) {
+        BlockHeader h;
+        h.i0 = h.i1 = h.j0 = h.j1 = -1;
+        h.count = -1;
+        h.pad[0] = h.pad[1] = h.pad[2] = -1;
+        header[t] = h;
+    }
+    if (t < ncell) carry[t] = 0ull;
+}
+
+// The scratch address on the current device and the pass kernels' LDS
+// limits, set up once per device.
+scpic_status static_scratch(unsigned char **out)
+{
+    int dev = 0;
+    SCPIC_HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SCPIC_EUNSUPPORTED, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    if (!g_static_ready[dev]) {
+        void *ptr = nullptr;
+        SCPIC_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        hipDeviceProp_t prop;
+        SCPIC_HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+        SCPIC_HIP_TRY(prepare_pass_kernels(prop.sharedMemPerBlock), "hipFuncSetAttribute");
+        g_static_ptr[dev] = (unsigned char *)ptr;
+        g_static_ready[dev] = true;
+    }
+    *out = g_static_ptr[dev];
+    return SCPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+scpic_status scpic_deposit_static(const scpic_grid *grid, const scpic_particles *parts,
+                                  int64_t *rho, int64_t *n_in, void *hip_stream)
+{
+    g_last_error.clear();
+    if (!grid) return fail(SCPIC_EINVAL, "grid is NULL");
+    if (scpic_status st = check_grid(grid)) return st;
+    if (scpic_status st = check_parts(parts)) return st;
+    if (!rho) return fail(SCPIC_EINVAL, "rho is NULL");
+    // a workgroup's header counts its particles in 32 bits
+    if (parts->n > (int64_t)kStaticBlocks * INT32_MAX)
+        return fail(SCPIC_EUNSUPPORTED, "at most 64 * (2^31 - 1) particles per call");
+    unsigned char *base = nullptr;
+    if (scpic_status st = static_scratch(&base)) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    DepositTarget dep;
+    dep.header = (BlockHeader *)base;
+    dep.carry = (unsigned long long *)(base + kStaticHeaderBytes);
+    dep.partial = (uint32_t *)(base + kStaticHeaderBytes + kStaticCarryBytes);
+    dep.max_blocks = kStaticBlocks;
+    const int ncell = grid->nx * grid->ny;
+    hipLaunchKernelGGL(k_static_clear, dim3((std::max(ncell, kStaticBlocks) + 255) / 256),
+                       dim3(256), 0, s, dep.header, dep.carry, ncell);
+    SCPIC_HIP_TRY(hipGetLastError(), "scratch clear launch");
+    GridGeom g;
+    g.nx = grid->nx;
+    g.ny = grid->ny;
+    g.x_min = grid->x_min;
+    g.y_min = grid->y_min;
+    g.inv_dx = 1.0 / grid->dx;
+    g.inv_dy = 1.0 / grid->dy;
+    constexpr int kThreads = 1024;
+    const int blocks =
+        parts->n > 0 ? (int)std::min<int64_t>(kStaticBlocks, (parts->n + kThreads - 1) / kThreads)
+                     : 0;
+    PassElements none;
+    std::memset(&none, 0, sizeof(none));
+    if (blocks > 0) {
+        ParticlePtrs p = to_ptrs(parts);
+        p.stream = false;
+        SCPIC_HIP_TRY(launch_pass(s, p, g, false, false, nullptr, 0.0, none, true, dep, blocks,
+                                  kThreads),
+                      "deposit pass launch");
+    }
+    SCPIC_HIP_TRY(launch_reduce(s, dep, blocks, grid->nx, grid->ny, rho, n_in), "reduce launch");
     return SCPIC_OK;
 }
 

@@ -34,7 +34,10 @@ EXPORTS = ("scpic_version", "scpic_last_error", "scpic_create", "scpic_destroy",
            "scpic_get_field", "scpic_batch_create", "scpic_batch_destroy",
            "scpic_batch_set_stream", "scpic_track_batched", "scpic_batch_autotune",
            "scpic_batch_get_field", "scpic_set_line_density", "scpic_get_line_state",
-           "scpic_get_potential", "scpic_diagnose")
+           "scpic_get_potential", "scpic_diagnose", "scpic_deposit_static")
+
+# bytes of the static device scratch behind scpic_deposit_static (per device)
+STATIC_SCRATCH_BYTES = 17303552
 
 
 class Grid(ctypes.Structure):
@@ -104,6 +107,8 @@ def load_library(path: Path | str | None = None):
     L.scpic_batch_autotune.argtypes = [vp, ctypes.POINTER(Particles), ctypes.POINTER(vp),
                                        ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
                                        ctypes.POINTER(i32)]
+    L.scpic_deposit_static.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Particles), vp, vp,
+                                       vp]
     for name in EXPORTS:
         if name not in ("scpic_version", "scpic_last_error"):
             getattr(L, name).restype = i32
@@ -182,6 +187,30 @@ def to_device(parts: dict, device="cuda") -> dict:
 
 def to_host(parts: dict) -> dict:
     return {k: v.cpu().numpy() for k, v in parts.items()}
+
+
+def _grid_struct(grid: dict) -> Grid:
+    return Grid(int(grid["nx"]), int(grid["ny"]), float(grid["x_min"]), float(grid["y_min"]),
+                float(grid["dx"]), float(grid["dy"]))
+
+
+def deposit_static(grid: dict, parts: dict, rho: torch.Tensor, n_in: torch.Tensor | None = None,
+                   stream=None):
+    """Allocation-free deposit (scpic_deposit_static) into caller-owned outputs:
+    rho, a contiguous int64 CUDA tensor of nx*ny entries, and optionally n_in,
+    one int64 on the same device.  Allocates nothing."""
+    L = load_library()
+    ncell = int(grid["nx"]) * int(grid["ny"])
+    if not (isinstance(rho, torch.Tensor) and rho.is_cuda and rho.dtype == torch.int64
+            and rho.is_contiguous() and rho.numel() == ncell):
+        raise TypeError("rho must be a contiguous int64 CUDA tensor of nx*ny entries")
+    if n_in is not None and not (n_in.is_cuda and n_in.dtype == torch.int64
+                                 and n_in.numel() == 1 and n_in.device == rho.device):
+        raise TypeError("n_in must be one int64 on rho's device")
+    g = _grid_struct(grid)
+    p = particles_struct(parts)
+    _check(L.scpic_deposit_static(ctypes.byref(g), ctypes.byref(p), rho.data_ptr(),
+                                  None if n_in is None else n_in.data_ptr(), _stream_ptr(stream)))
 
 
 class Context:

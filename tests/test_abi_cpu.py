@@ -125,3 +125,31 @@ def test_batch_calls_on_null_batch_are_einval(lib):
     assert lib.scpic_batch_get_field(None, 0, None, None) == -1
     assert lib.scpic_batch_autotune(None, ctypes.byref(p), None, None, 1, None, None) == -1
     assert b"batch" in lib.scpic_last_error()
+
+
+def test_static_deposit_rejects_bad_arguments_before_touching_the_device(lib):
+    from paper_2010_11540_amd.scpic import Particles
+    p = Particles(None, None, None, None, None, None, 0)
+    neg = Particles(None, None, None, None, None, None, -1)
+    nulls = Particles(None, None, None, None, None, None, 5)
+    rho = ctypes.c_void_p(0x1000)
+    g = _grid()
+    assert lib.scpic_deposit_static(None, ctypes.byref(p), rho, None, None) == -1
+    assert lib.scpic_deposit_static(ctypes.byref(g), None, rho, None, None) == -1
+    assert lib.scpic_deposit_static(ctypes.byref(g), ctypes.byref(p), None, None, None) == -1
+    assert lib.scpic_deposit_static(ctypes.byref(g), ctypes.byref(neg), rho, None, None) == -1
+    assert lib.scpic_deposit_static(ctypes.byref(g), ctypes.byref(nulls), rho, None, None) == -1
+    for kw, code in (({"nx": 257}, -4), ({"ny": 102}, -4), ({"dx": 0.0}, -1)):
+        bad = _grid(**kw)
+        assert lib.scpic_deposit_static(ctypes.byref(bad), ctypes.byref(p), rho, None, None) == code
+        assert lib.scpic_last_error()
+
+
+def test_static_scratch_size_matches_the_header():
+    from paper_2010_11540_amd import scpic
+    text = HEADER.read_text()
+    m = re.search(r"#define SCPIC_STATIC_SCRATCH_BYTES (\d+)", text)
+    assert m and int(m.group(1)) == scpic.STATIC_SCRATCH_BYTES
+    # 64 workgroups' uint32 partials of a 65536-node grid, their 32-byte
+    # headers and a uint64 carry grid of 65536 nodes
+    assert scpic.STATIC_SCRATCH_BYTES == 64 * 65536 * 4 + 64 * 32 + 65536 * 8
