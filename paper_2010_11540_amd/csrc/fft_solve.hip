@@ -56,24 +56,35 @@ __device__ __forceinline__ cx<T> mul_neg_i(cx<T> a) { return {a.im, -a.re}; }
 template <typename T>
 __device__ __forceinline__ cx<T> mul_pos_i(cx<T> a) { return {-a.im, a.re}; }
 
-// Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L) of the sequence in LDS
-// buffer a (length L = 2^log2L), computed by threads tid = 0..nthr-1 of a
-// group, ping-ponging with buffer b.  Every thread of the workgroup must call
-// it the same number of times (it synchronises the workgroup between
-// stages).  Stockham autosort: one radix-2 stage first when log2L is odd, then
-// radix-4 stages; each stage reads sub-transform inputs L/r apart, applies the
-// twiddles exp(-2 pi i m k / (Ns r)) and writes the r outputs Ns apart.
-// tw[t * tws] = exp(-2 pi i t / L).  Returns the buffer holding X in natural
-// order.
-template <typename T>
-__device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw, int tws, int tid,
-                          int nthr)
+// Orders one wave's LDS accesses across an FFT stage: a wave's LDS
+// instructions execute in order, so the fences only stop the compiler from
+// moving a read of the next stage above a write of this one.
+__device__ __forceinline__ void wave_lds_order()
 {
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L) of the sequence in LDS
+// buffer a (length L = 2^log2L), ping-ponging with buffer b, computed by ONE
+// wave: lane = 0..63 of that wave (a lane index >= L/2 takes no butterfly,
+// which lets the other waves of a workgroup call it too, as a no-op).  The
+// input must be visible to the wave when it is called (a workgroup barrier if
+// other waves wrote it); the result is visible to the same wave on return and
+// to the others after a workgroup barrier.  Stockham autosort: one radix-2
+// stage first when log2L is odd, then radix-4 stages; each stage reads
+// sub-transform inputs L/r apart, applies the twiddles exp(-2 pi i m k / (Ns r))
+// and writes the r outputs Ns apart.  tw[t * tws] = exp(-2 pi i t / L).
+// Returns the buffer holding X in natural order (the same in every lane).
+template <typename T>
+__device__ cx<T> *fft_wave(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw, int tws,
+                           int lane)
+{
     int ns = 1;
     if (log2L & 1) {
         const int h = L >> 1;
-        for (int j = tid; j < h; j += nthr) {
+        for (int j = lane; j < h; j += 64) {
             const cx<T> u = a[j], v = a[j + h];
             b[2 * j] = u + v;
             b[2 * j + 1] = u - v;
@@ -82,13 +93,13 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw,
         a = b;
         b = t;
         ns = 2;
-        __syncthreads();
+        wave_lds_order();
     }
     const int q = L >> 2;
     int span = L >> 2;  // L / (4 ns)
     if (log2L & 1) span >>= 1;
     while (ns < L) {
-        for (int j = tid; j < q; j += nthr) {
+        for (int j = lane; j < q; j += 64) {
             const int k = j & (ns - 1);
             const int step = span * k * tws;
             const cx<T> a0 = a[j];
@@ -107,7 +118,7 @@ __device__ cx<T> *fft_lds(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw,
         b = t;
         ns *= 4;
         span >>= 2;
-        __syncthreads();
+        wave_lds_order();
     }
     return a;
 }
@@ -123,8 +134,8 @@ constexpr int kMaxPerThread = kMaxFft / 64;
 // ny/4 lanes cover one workgroup's row segment and the kRowThreads/(ny/4)
 // groups of lanes split the workgroups, each issuing all of its loads before
 // adding any (one round of memory latency for <= kReduceChunk workgroups per
-// lane).  Chunks outside a workgroup's bounding box are not read; cells of a
-// chunk outside it are masked.  hdr: the headers staged in LDS; red: LDS
+// lane).  Chunks outside a workgroup's bounding box are not read (their
+// loads return zeros without touching memory).  hdr: the headers staged in LDS; red: LDS
 // scratch of NT * 4 uint64; carry_v: this cell's carry, loaded by
 // the caller with its first round of loads (cleared here when nonzero).
 // Returns the total of cell tid (tid < ny).
@@ -158,32 +169,38 @@ __device__ __forceinline__ unsigned long long reduce_row(const DepositTarget &de
     const int groups = L.groups, grp = L.grp, j0c = L.j0c;
     // when ny / 4 does not divide NT the last threads form no whole group
     const bool member = grp < groups;
+    // The partials as a buffer: a chunk outside a workgroup's box is read at
+    // an offset past the buffer's end, which returns zeros and touches no
+    // memory.  A chunk inside the box holds the box's cells and zeros (the
+    // tile's cells outside the box are zero), so no cell needs a mask.
+    const uint32_t bytes = (uint32_t)(sizeof(uint32_t) * (size_t)dep.max_blocks * ny) *
+                           (uint32_t)(i + 1);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(dep.partial, (short)0, (int)bytes, 0x00020000);
+    constexpr uint32_t kOutside = 0x80000000u;
+    const uint32_t row0 = (uint32_t)(sizeof(uint32_t) * ((size_t)i * dep.max_blocks * ny + j0c));
     unsigned long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    const uint32_t *row = dep.partial + (size_t)i * dep.max_blocks * ny + j0c;
     for (int b0 = member ? grp : nblocks; b0 < nblocks; b0 += groups * kReduceChunk) {
-        uint4 v[kReduceChunk];
-        int lo[kReduceChunk], hi[kReduceChunk];
-        // Branch-free: every lane issues its loads back to back (a chunk
-        // outside a workgroup's box is read from workgroup 0's slice, always
-        // valid and usually cached, and masked), so the compiler does not
-        // wait between them.
+        uint32_t off[kReduceChunk];
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
             const int b = b0 + u * groups;
-            const int bc = b < nblocks ? b : 0;
-            const BlockHeader h = hdr[bc];
+            const BlockHeader h = hdr[b < nblocks ? b : 0];
             const bool take = b < nblocks && i >= h.i0 && i <= h.i1 && j0c + 3 >= h.j0 &&
                               j0c <= h.j1;
-            lo[u] = take ? h.j0 : 0;
-            hi[u] = take ? h.j1 : -1;
-            v[u] = *reinterpret_cast<const uint4 *>(row + (size_t)(take ? bc : 0) * ny);
+            off[u] = take ? row0 + (uint32_t)(sizeof(uint32_t) * (size_t)b * ny) : kOutside;
         }
+        // every load in flight before the first add
+        decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0)) v[kReduceChunk];
+#pragma unroll
+        for (int u = 0; u < kReduceChunk; ++u)
+            v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off[u], 0, 0);
 #pragma unroll
         for (int u = 0; u < kReduceChunk; ++u) {
-            s0 += (j0c + 0 >= lo[u] && j0c + 0 <= hi[u]) ? v[u].x : 0u;
-            s1 += (j0c + 1 >= lo[u] && j0c + 1 <= hi[u]) ? v[u].y : 0u;
-            s2 += (j0c + 2 >= lo[u] && j0c + 2 <= hi[u]) ? v[u].z : 0u;
-            s3 += (j0c + 3 >= lo[u] && j0c + 3 <= hi[u]) ? v[u].w : 0u;
+            s0 += (uint32_t)v[u][0];
+            s1 += (uint32_t)v[u][1];
+            s2 += (uint32_t)v[u][2];
+            s3 += (uint32_t)v[u][3];
         }
     }
     if (member) {
@@ -278,7 +295,10 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
         return l < ny ? rho[l] : -rho[my - l];
     };
     if (tid < half) a[tid] = cx<T>{sample(2 * tid), sample(2 * tid + 1)};
-    const cx<T> *Z = fft_lds(a, b, half, log2my - 1, twl, 2, tid, NT);
+    __syncthreads();
+    // wave 0 transforms; the other waves only learn where the result lies
+    const cx<T> *Z = fft_wave(a, b, half, log2my - 1, twl, 2, tid < 64 ? tid : half);
+    __syncthreads();
     for (int l = tid; l <= half; l += NT) {
         const cx<T> zl = Z[l & (half - 1)];
         const cx<T> zm = conj(Z[(half - l) & (half - 1)]);
@@ -426,7 +446,9 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
             a[k] = va[r];
         }
     }
-    const cx<T> *r0 = fft_lds(a, b, mx, log2mx, twl, 1, tid, kColThreads);
+    __syncthreads();
+    const cx<T> *r0 = fft_wave(a, b, mx, log2mx, twl, 1, tid < 64 ? tid : mx);
+    __syncthreads();
     // Inverse transforms as conj(FFT(conj(.))): stage the conjugated inputs,
     // x difference in c, y part in d.
 #pragma unroll
@@ -439,11 +461,13 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
         }
     }
     const int wave = tid >> 6, lane = tid & 63;
+    __syncthreads();
+    // waves 0 and 1 run the two inverse transforms side by side; waves 2 and
+    // 3 only helped load and stage
+    if (wave >= 2) return;
     cx<T> *in = wave ? d : c;
     cx<T> *tmp = wave ? b : a;
-    // waves 2 and 3 (loads and the forward transform only) pass a lane index
-    // past every butterfly, so they only keep the barriers
-    const cx<T> *res = fft_lds(in, tmp, mx, log2mx, twl, 1, wave < 2 ? lane : mx, 64);
+    const cx<T> *res = fft_wave(in, tmp, mx, log2mx, twl, 1, lane);
     if (wave == 0) {
         for (int i = lane; i < nx; i += 64) bx[(size_t)i * (hy + 1) + l] = conj(res[i]);
     } else if (wave == 1) {
@@ -530,31 +554,37 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
             if (l > 0 && l < hy) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
         }
     }
-    const bool field_row = i >= 0 && i < nx;
-    if (field_row) {
-        const cx<T> *r = fft_lds(a, b, my, log2my, twl, 1, tid, kInvThreads);
-        if (ef) {
-            for (int j = tid; j < ny; j += kInvThreads) ef[(size_t)i * ny + j] = conj(r[j]);
-        } else {
-            for (int j = tid; j < ny; j += kInvThreads) {
-                const cx<T> z = conj(r[j]);
-                ex[(size_t)i * ny + j] = z.re;
-                ey[(size_t)i * ny + j] = z.im;
-            }
-        }
-    }
+    // the potential's row (with bp) is staged beside the field's
+    cx<T> *a2 = b + my;
+    cx<T> *b2 = a2 + my;
     if (bp) {
-        cx<T> *a2 = b + my;
-        cx<T> *b2 = a2 + my;
         const cx<T> *rp = bp + (size_t)(i + 1) * (hy + 1);
         for (int l = tid; l <= hy; l += kInvThreads) {
             const cx<T> P = rp[l];
             a2[l] = conj(P);
             if (l > 0 && l < hy) a2[my - l] = P;
         }
-        const cx<T> *r2 = fft_lds(a2, b2, my, log2my, twl, 1, tid, kInvThreads);
+    }
+    __syncthreads();
+    // wave 0 transforms and stores the field row, wave 1 the potential's
+    const int wave = tid >> 6, lane = tid & 63;
+    const bool field_row = i >= 0 && i < nx;
+    if (wave == 0 && field_row) {
+        const cx<T> *r = fft_wave(a, b, my, log2my, twl, 1, lane);
+        if (ef) {
+            for (int j = lane; j < ny; j += 64) ef[(size_t)i * ny + j] = conj(r[j]);
+        } else {
+            for (int j = lane; j < ny; j += 64) {
+                const cx<T> z = conj(r[j]);
+                ex[(size_t)i * ny + j] = z.re;
+                ey[(size_t)i * ny + j] = z.im;
+            }
+        }
+    }
+    if (wave == 1 && bp) {
+        const cx<T> *r2 = fft_wave(a2, b2, my, log2my, twl, 1, lane);
         T *row = phi + (size_t)(i + 1) * (ny + 2);
-        for (int j = tid - 1; j <= ny; j += kInvThreads) row[j + 1] = r2[j < 0 ? my - 1 : j].re;
+        for (int j = lane - 1; j <= ny; j += 64) row[j + 1] = r2[j < 0 ? my - 1 : j].re;
     }
 }
 
