@@ -1177,10 +1177,21 @@ scpic_status batch_layout(scpic_batch *b, int threads, int blocks_per_cu)
     for (int k = 0; k < b->n_inst; ++k) sizes[k] = b->inst[k].n;
     const std::vector<int> blocks =
         batch_assign_blocks(sizes, (int64_t)b->n_cu * blocks_per_cu, threads, b->max_slices);
+    // Workgroups are dispatched in index order as compute units free up, so
+    // the beams whose workgroups carry the most particles go first and the
+    // lightest fill the end of the launch (longest first keeps the tail short).
+    // A beam's workgroups stay contiguous; results do not depend on the order.
+    std::vector<int> order(b->n_inst);
+    for (int k = 0; k < b->n_inst; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+        const double lu = blocks[u] ? (double)sizes[u] / blocks[u] : 0.0;
+        const double lv = blocks[v] ? (double)sizes[v] / blocks[v] : 0.0;
+        return lu > lv;
+    });
     std::vector<uint16_t> pass_inst;
     b->total_pass_blocks = 0;
     b->max_beam_blocks = 0;
-    for (int k = 0; k < b->n_inst; ++k) {
+    for (int k : order) {
         BatchInstance &I = b->inst[k];
         I.pass_blocks = blocks[k];
         I.pass_block0 = b->total_pass_blocks;
@@ -1241,15 +1252,9 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         b->max_slices[k] = std::max(
             1, batch_pass_blocks(n_k, total, (int64_t)b->n_cu * kMaxTuneBlocksPerCu, kMinTuneThreads));
         pass_table_len += (size_t)b->max_slices[k];
-        I.row_block0 = b->total_rows;
-        b->total_rows += nx;
-        I.col_block0 = b->total_cols;
-        b->total_cols += fft_len(ny) / 2 + 1;
         b->max_mx = std::max(b->max_mx, fft_len(nx));
         b->max_ny = std::max(b->max_ny, ny);
         b->max_my = std::max(b->max_my, fft_len(ny));
-        for (int t = 0; t < nx; ++t) row_inst.push_back((uint16_t)k);
-        for (int t = 0; t <= fft_len(ny) / 2; ++t) col_inst.push_back((uint16_t)k);
         I.g.nx = nx;
         I.g.ny = ny;
         I.g.x_min = gr.x_min;
@@ -1298,6 +1303,25 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         SCPIC_HIP_TRY(hipMemset(I.dep.carry, 0, sizeof(unsigned long long) * ncell), "hipMemset");
         SCPIC_HIP_TRY(hipMemset(I.dep.header, 0xff, sizeof(BlockHeader) * slices), "hipMemset");
         SCPIC_HIP_TRY(hipMemset(I.ef, 0, 2 * fe * ncell), "hipMemset");
+    }
+    // Grid-phase workgroups in index order: the beams with the largest grids
+    // and the most particles (more partial slices to sum) first, so that the
+    // quick ones fill the end of each launch.
+    std::vector<int> order(n_inst);
+    for (int k = 0; k < n_inst; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int u, int v) {
+        const int64_t cu = (int64_t)grids[u].nx * grids[u].ny, cv = (int64_t)grids[v].nx * grids[v].ny;
+        if (cu != cv) return cu > cv;
+        return offsets[u + 1] - offsets[u] > offsets[v + 1] - offsets[v];
+    });
+    for (int k : order) {
+        BatchInstance &I = b->inst[k];
+        I.row_block0 = b->total_rows;
+        b->total_rows += I.nx;
+        I.col_block0 = b->total_cols;
+        b->total_cols += I.my / 2 + 1;
+        for (int t = 0; t < I.nx; ++t) row_inst.push_back((uint16_t)k);
+        for (int t = 0; t <= I.my / 2; ++t) col_inst.push_back((uint16_t)k);
     }
     BatchInstance *inst_dev;
     uint16_t *pass_dev, *row_dev, *col_dev;
