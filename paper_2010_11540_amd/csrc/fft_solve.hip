@@ -66,6 +66,13 @@ __device__ __forceinline__ void wave_lds_order()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// LDS slot of element e of an FFT buffer: e with bits 0-4 XORed by bits 2-6
+// (a permutation within each aligned block of 32 elements, and of any
+// shorter buffer).  With it the strided writes of the early FFT stages (and
+// their reads) fall on distinct banks, which the natural order does not:
+// there a stage's outputs are written 4 ns elements apart per lane.
+__device__ __forceinline__ int sw(int e) { return e ^ ((e >> 2) & 31); }
+
 // Forward DFT X[k] = sum_n x[n] exp(-2 pi i n k / L) of the sequence in LDS
 // buffer a (length L = 2^log2L), ping-ponging with buffer b, computed by ONE
 // wave: lane = 0..63 of that wave (a lane index >= L/2 takes no butterfly,
@@ -75,19 +82,19 @@ __device__ __forceinline__ void wave_lds_order()
 // to the others after a workgroup barrier.  Stockham autosort: one radix-2
 // stage first when log2L is odd, then radix-4 stages; each stage reads
 // sub-transform inputs L/r apart, applies the twiddles exp(-2 pi i m k / (Ns r))
-// and writes the r outputs Ns apart.  tw[t * tws] = exp(-2 pi i t / L).
+// and writes the r outputs Ns apart.  st: the stage twiddles of an L-point
+// FFT (stage_twiddle_count), in LDS.
 // Returns the buffer holding X in natural order (the same in every lane).
 template <typename T>
-__device__ cx<T> *fft_wave(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw, int tws,
-                           int lane)
+__device__ cx<T> *fft_wave(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *st, int lane)
 {
     int ns = 1;
     if (log2L & 1) {
         const int h = L >> 1;
         for (int j = lane; j < h; j += 64) {
-            const cx<T> u = a[j], v = a[j + h];
-            b[2 * j] = u + v;
-            b[2 * j + 1] = u - v;
+            const cx<T> u = a[sw(j)], v = a[sw(j + h)];
+            b[sw(2 * j)] = u + v;
+            b[sw(2 * j + 1)] = u - v;
         }
         cx<T> *t = a;
         a = b;
@@ -95,29 +102,28 @@ __device__ cx<T> *fft_wave(cx<T> *a, cx<T> *b, int L, int log2L, const cx<T> *tw
         ns = 2;
         wave_lds_order();
     }
+    const int c = ns;
     const int q = L >> 2;
-    int span = L >> 2;  // L / (4 ns)
-    if (log2L & 1) span >>= 1;
     while (ns < L) {
+        const cx<T> *ws = st + (ns - c);
         for (int j = lane; j < q; j += 64) {
             const int k = j & (ns - 1);
-            const int step = span * k * tws;
-            const cx<T> a0 = a[j];
-            const cx<T> a1 = cmul(a[j + q], tw[step]);
-            const cx<T> a2 = cmul(a[j + 2 * q], tw[2 * step]);
-            const cx<T> a3 = cmul(a[j + 3 * q], tw[3 * step]);
+            const cx<T> *w = ws + 3 * k;
+            const cx<T> a0 = a[sw(j)];
+            const cx<T> a1 = cmul(a[sw(j + q)], w[0]);
+            const cx<T> a2 = cmul(a[sw(j + 2 * q)], w[1]);
+            const cx<T> a3 = cmul(a[sw(j + 3 * q)], w[2]);
             const cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = a1 - a3;
             const int base = (j - k) * 4 + k;
-            b[base] = t0 + t2;
-            b[base + ns] = t1 + mul_neg_i(t3);
-            b[base + 2 * ns] = t0 - t2;
-            b[base + 3 * ns] = t1 + mul_pos_i(t3);
+            b[sw(base)] = t0 + t2;
+            b[sw(base + ns)] = t1 + mul_neg_i(t3);
+            b[sw(base + 2 * ns)] = t0 - t2;
+            b[sw(base + 3 * ns)] = t1 + mul_pos_i(t3);
         }
         cx<T> *t = a;
         a = b;
         b = t;
         ns *= 4;
-        span >>= 2;
         wave_lds_order();
     }
     return a;
@@ -246,13 +252,15 @@ __global__ void __launch_bounds__(kRowThreads)
 // grid), real and zero-padded to my = 2 hy: packed z[m] = rho[2m] + i rho[2m+1]
 // (zero from index ny on), Z = FFT_hy(z), then
 //   X[l] = (Z[l] + conj Z[hy-l]) / 2 - i W^l (Z[l] - conj Z[hy-l]) / 2,
-// W = exp(-2 pi i / my), for l = 0..hy.
-// LDS of the row-forward workgroup: twiddles [my], two FFT buffers [hy],
-// rho [ny], then (16-byte aligned) the staged headers.
+// W = exp(-2 pi i / my), for l = 0..hy.  tw: W^l for l = 0..hy, then the
+// stage twiddles of the hy-point FFT (the grid's stw_y table).
+// LDS of the row-forward workgroup: the twiddles W^l, l = 0..hy, the stage
+// twiddles of the hy-point FFT [hy], two FFT buffers [hy], rho [ny], then
+// (16-byte aligned) the staged headers.
 template <typename T>
 __host__ __device__ constexpr size_t rows_fwd_hdr_offset(int ny, int my)
 {
-    return (sizeof(cx<T>) * (size_t)(2 * my) + sizeof(T) * (size_t)ny + 15) & ~(size_t)15;
+    return (sizeof(cx<T>) * (size_t)(2 * my + 1) + sizeof(T) * (size_t)ny + 15) & ~(size_t)15;
 }
 
 template <typename T, bool FROM_PARTIALS, int NT>
@@ -264,8 +272,9 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
 {
     extern __shared__ unsigned char smem_raw[];
     const int half = my >> 1;                           // hy: complex FFT length
-    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // my entries
-    cx<T> *a = twl + my;                                // hy
+    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);  // W^l, l = 0..hy
+    cx<T> *st = twl + half + 1;                         // stage twiddles, hy
+    cx<T> *a = st + half;                               // hy
     cx<T> *b = a + half;                                // hy
     T *rho = reinterpret_cast<T *>(b + half);           // ny
     BlockHeader *hdr = reinterpret_cast<BlockHeader *>(smem_raw + rows_fwd_hdr_offset<T>(ny, my));
@@ -275,7 +284,8 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
     const int64_t qv = (!FROM_PARTIALS && tid < ny) ? q[(size_t)i * ny + tid] : 0;
     const unsigned long long cv =
         (FROM_PARTIALS && tid < ny) ? dep.carry[(size_t)i * ny + tid] : 0ull;
-    for (int t = tid; t < my; t += NT) twl[t] = tw[t];
+    // W^l for l <= hy and the hy-point FFT's stage twiddles, as stored
+    for (int t = tid; t <= half + stage_twiddle_count(half, log2my - 1); t += NT) twl[t] = tw[t];
     if (FROM_PARTIALS)
         for (int t = tid; t < nblocks; t += NT) hdr[t] = dep.header[t];
     if (FROM_PARTIALS) {
@@ -294,14 +304,14 @@ __device__ __forceinline__ void rows_fwd_body(const DepositTarget &dep, int nblo
         if (i == 0 || l == 0 || l == ny) return T(0);
         return l < ny ? rho[l] : -rho[my - l];
     };
-    if (tid < half) a[tid] = cx<T>{sample(2 * tid), sample(2 * tid + 1)};
+    if (tid < half) a[sw(tid)] = cx<T>{sample(2 * tid), sample(2 * tid + 1)};
     __syncthreads();
     // wave 0 transforms; the other waves only learn where the result lies
-    const cx<T> *Z = fft_wave(a, b, half, log2my - 1, twl, 2, tid < 64 ? tid : half);
+    const cx<T> *Z = fft_wave(a, b, half, log2my - 1, st, tid < 64 ? tid : half);
     __syncthreads();
     for (int l = tid; l <= half; l += NT) {
-        const cx<T> zl = Z[l & (half - 1)];
-        const cx<T> zm = conj(Z[(half - l) & (half - 1)]);
+        const cx<T> zl = Z[sw(l & (half - 1))];
+        const cx<T> zm = conj(Z[sw((half - l) & (half - 1))]);
         const cx<T> s = zl + zm, d = zl - zm;
         const cx<T> wd = mul_neg_i(cmul(twl[l], d));
         at[(size_t)l * nx + i] = scale_c(s + wd, T(0.5));
@@ -391,7 +401,7 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
 {
     const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
     rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
-                                             I.my, I.log2_my, (const cx<T> *)I.tw_y,
+                                             I.my, I.log2_my, (const cx<T> *)I.stw_y,
                                              (cx<T> *)I.spec_a, (int)blockIdx.x - I.row_block0,
                                              false);
 }
@@ -399,7 +409,8 @@ __global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaun
 // Column l (of hy + 1) of the row spectra: forward FFT along x, times the
 // Green's spectrum, then the two differentiated inverse transforms, one per
 // wave.  The second is the column-inverse of the potential's spectrum before
-// the y difference; bp, when not null, receives it as well for the node
+// the y difference (tw: the stage twiddles of the mx-point FFT); bp, when
+// not null, receives it as well for the node
 // potential, on rows -1..nx (row i at bp[(i + 1) * (hy + 1)]; row -1 is the
 // periodic row mx - 1, which the zero padding or the odd extension makes the
 // potential's value one node outside the grid).
@@ -412,8 +423,8 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
                                           cx<T> *__restrict__ bp = nullptr)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *a = twl + mx;
+    cx<T> *st = reinterpret_cast<cx<T> *>(smem_raw);  // stage twiddles
+    cx<T> *a = st + mx;
     cx<T> *b = a + mx;
     cx<T> *c = b + mx;
     cx<T> *d = c + mx;
@@ -427,7 +438,7 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int k = tid + r * kColThreads;
-        vt[r] = k < mx ? tw[k] : cx<T>{T(0), T(0)};
+        vt[r] = k < stage_twiddle_count(mx, log2mx) ? tw[k] : cx<T>{T(0), T(0)};
         vg[r] = k < mx ? g[k] : T(0);
         vs[r] = k < mx ? sx[k] : T(0);
         // zero-padded column (open boundary), or its odd extension about
@@ -442,12 +453,12 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     for (int r = 0; r < kPer; ++r) {
         const int k = tid + r * kColThreads;
         if (k < mx) {
-            twl[k] = vt[r];
-            a[k] = va[r];
+            st[k] = vt[r];
+            a[sw(k)] = va[r];
         }
     }
     __syncthreads();
-    const cx<T> *r0 = fft_wave(a, b, mx, log2mx, twl, 1, tid < 64 ? tid : mx);
+    const cx<T> *r0 = fft_wave(a, b, mx, log2mx, st, tid < 64 ? tid : mx);
     __syncthreads();
     // Inverse transforms as conj(FFT(conj(.))): stage the conjugated inputs,
     // x difference in c, y part in d.
@@ -455,9 +466,9 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     for (int r = 0; r < kPer; ++r) {
         const int k = tid + r * kColThreads;
         if (k < mx) {
-            const cx<T> phi = scale_c(r0[k], vg[r]);
-            c[k] = conj(mul_neg_i(scale_c(phi, vs[r])));
-            d[k] = conj(phi);
+            const cx<T> phi = scale_c(r0[sw(k)], vg[r]);
+            c[sw(k)] = conj(mul_neg_i(scale_c(phi, vs[r])));
+            d[sw(k)] = conj(phi);
         }
     }
     const int wave = tid >> 6, lane = tid & 63;
@@ -467,15 +478,15 @@ __device__ __forceinline__ void cols_body(const cx<T> *__restrict__ at, int nx, 
     if (wave >= 2) return;
     cx<T> *in = wave ? d : c;
     cx<T> *tmp = wave ? b : a;
-    const cx<T> *res = fft_wave(in, tmp, mx, log2mx, twl, 1, lane);
+    const cx<T> *res = fft_wave(in, tmp, mx, log2mx, st, lane);
     if (wave == 0) {
-        for (int i = lane; i < nx; i += 64) bx[(size_t)i * (hy + 1) + l] = conj(res[i]);
+        for (int i = lane; i < nx; i += 64) bx[(size_t)i * (hy + 1) + l] = conj(res[sw(i)]);
     } else if (wave == 1) {
         for (int i = lane; i < nx; i += 64)
-            by[(size_t)i * (hy + 1) + l] = mul_neg_i(scale_c(conj(res[i]), syl));
+            by[(size_t)i * (hy + 1) + l] = mul_neg_i(scale_c(conj(res[sw(i)]), syl));
         if (bp)
             for (int i = lane - 1; i <= nx; i += 64)
-                bp[(size_t)(i + 1) * (hy + 1) + l] = conj(res[i < 0 ? mx - 1 : i]);
+                bp[(size_t)(i + 1) * (hy + 1) + l] = conj(res[sw(i < 0 ? mx - 1 : i)]);
     }
 }
 
@@ -493,14 +504,14 @@ template <typename T>
 __global__ void __launch_bounds__(kColThreads) k_cols_batched(BatchLaunch b)
 {
     const BatchInstance &I = b.inst[b.col_inst[blockIdx.x]];
-    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.my >> 1, I.mx, I.log2_mx, (const cx<T> *)I.tw_x,
+    cols_body<T>((const cx<T> *)I.spec_a, I.nx, I.my >> 1, I.mx, I.log2_mx, (const cx<T> *)I.stw_x,
                  (const T *)I.ghat_t, (const T *)I.sx, (const T *)I.sy, (cx<T> *)I.spec_bx,
                  (cx<T> *)I.spec_by, (int)blockIdx.x - I.col_block0, false);
 }
 
 // Row i: Z[l] = Bx[l] + i By[l] for l = 0..hy and Z[my-l] = conj(Bx[l]) +
 // i conj(By[l]) for 0 < l < hy (hy = my / 2); one inverse FFT gives ex + i ey
-// on the first ny entries.  Written
+// on the first ny entries (tw: the stage twiddles of the my-point FFT).  Written
 // either as two arrays (ex, ey) or interleaved into ef (Ex, Ey per node).
 // With bp (the potential's column-inverse spectrum), a second inverse FFT of
 // its Hermitian row writes row i of the node potential phi on columns
@@ -516,8 +527,8 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
                                               T *__restrict__ phi = nullptr)
 {
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *twl = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *a = twl + my;
+    cx<T> *st = reinterpret_cast<cx<T> *>(smem_raw);  // stage twiddles
+    cx<T> *a = st + my;
     cx<T> *b = a + my;
     const int tid = threadIdx.x;
     const int hy = my >> 1;
@@ -531,7 +542,7 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
 #pragma unroll
     for (int r = 0; r < kPerT; ++r) {
         const int t = tid + r * kInvThreads;
-        vt[r] = t < my ? tw[t] : cx<T>{T(0), T(0)};
+        vt[r] = t < stage_twiddle_count(my, log2my) ? tw[t] : cx<T>{T(0), T(0)};
     }
 #pragma unroll
     for (int r = 0; r < kPerL; ++r) {
@@ -542,7 +553,7 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
 #pragma unroll
     for (int r = 0; r < kPerT; ++r) {
         const int t = tid + r * kInvThreads;
-        if (t < my) twl[t] = vt[r];
+        if (t < my) st[t] = vt[r];
     }
 #pragma unroll
     for (int r = 0; r < kPerL; ++r) {
@@ -550,8 +561,8 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
         if (l <= hy) {
             const cx<T> X = vx[r], Y = vy[r];
             // conjugated inputs for conj(FFT(conj(.)))
-            a[l] = conj(X + mul_pos_i(Y));
-            if (l > 0 && l < hy) a[my - l] = conj(conj(X) + mul_pos_i(conj(Y)));
+            a[sw(l)] = conj(X + mul_pos_i(Y));
+            if (l > 0 && l < hy) a[sw(my - l)] = conj(conj(X) + mul_pos_i(conj(Y)));
         }
     }
     // the potential's row (with bp) is staged beside the field's
@@ -561,8 +572,8 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
         const cx<T> *rp = bp + (size_t)(i + 1) * (hy + 1);
         for (int l = tid; l <= hy; l += kInvThreads) {
             const cx<T> P = rp[l];
-            a2[l] = conj(P);
-            if (l > 0 && l < hy) a2[my - l] = P;
+            a2[sw(l)] = conj(P);
+            if (l > 0 && l < hy) a2[sw(my - l)] = P;
         }
     }
     __syncthreads();
@@ -570,21 +581,21 @@ __device__ __forceinline__ void rows_inv_body(const cx<T> *__restrict__ bx,
     const int wave = tid >> 6, lane = tid & 63;
     const bool field_row = i >= 0 && i < nx;
     if (wave == 0 && field_row) {
-        const cx<T> *r = fft_wave(a, b, my, log2my, twl, 1, lane);
+        const cx<T> *r = fft_wave(a, b, my, log2my, st, lane);
         if (ef) {
-            for (int j = lane; j < ny; j += 64) ef[(size_t)i * ny + j] = conj(r[j]);
+            for (int j = lane; j < ny; j += 64) ef[(size_t)i * ny + j] = conj(r[sw(j)]);
         } else {
             for (int j = lane; j < ny; j += 64) {
-                const cx<T> z = conj(r[j]);
+                const cx<T> z = conj(r[sw(j)]);
                 ex[(size_t)i * ny + j] = z.re;
                 ey[(size_t)i * ny + j] = z.im;
             }
         }
     }
     if (wave == 1 && bp) {
-        const cx<T> *r2 = fft_wave(a2, b2, my, log2my, twl, 1, lane);
+        const cx<T> *r2 = fft_wave(a2, b2, my, log2my, st, lane);
         T *row = phi + (size_t)(i + 1) * (ny + 2);
-        for (int j = lane - 1; j <= ny; j += 64) row[j + 1] = r2[j < 0 ? my - 1 : j].re;
+        for (int j = lane - 1; j <= ny; j += 64) row[j + 1] = r2[sw(j < 0 ? my - 1 : j)].re;
     }
 }
 
@@ -605,7 +616,7 @@ __global__ void __launch_bounds__(kInvThreads) k_rows_inv_batched(BatchLaunch b)
 {
     const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
     rows_inv_body<T>((const cx<T> *)I.spec_bx, (const cx<T> *)I.spec_by, I.nx, I.ny, I.my,
-                     I.log2_my, (const cx<T> *)I.tw_y, nullptr, nullptr, (cx<T> *)I.ef,
+                     I.log2_my, (const cx<T> *)I.stw_y + I.my + 1, nullptr, nullptr, (cx<T> *)I.ef,
                      (int)blockIdx.x - I.row_block0);
 }
 
@@ -617,14 +628,14 @@ hipError_t launch_tail(hipStream_t s, const SolveWorkspace &w, void *ex, void *e
     const size_t inv_lds = (want_phi ? 5 : 3) * sizeof(cx<T>) * (size_t)w.my;
     cx<T> *bp = want_phi ? (cx<T> *)w.spec_p : nullptr;
     hipLaunchKernelGGL(k_cols<T>, dim3(w.my / 2 + 1), dim3(kColThreads), col_lds, s,
-                       (const cx<T> *)w.spec_a, w.nx, w.my / 2, w.mx, w.log2_mx, (const cx<T> *)w.tw_x,
+                       (const cx<T> *)w.spec_a, w.nx, w.my / 2, w.mx, w.log2_mx, (const cx<T> *)w.stw_x,
                        (const T *)w.ghat_t, (const T *)w.sx, (const T *)w.sy, (cx<T> *)w.spec_bx,
                        (cx<T> *)w.spec_by, w.pipe, bp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rows_inv<T>, dim3(w.nx + (want_phi ? 2 : 0)), dim3(kInvThreads), inv_lds, s,
                        (const cx<T> *)w.spec_bx, (const cx<T> *)w.spec_by, w.nx, w.ny, w.my,
-                       w.log2_my, (const cx<T> *)w.tw_y, (T *)ex, (T *)ey, (cx<T> *)ef,
+                       w.log2_my, (const cx<T> *)w.stw_y + w.my + 1, (T *)ex, (T *)ey, (cx<T> *)ef,
                        (const cx<T> *)bp, want_phi ? (T *)w.phi : (T *)nullptr);
     return hipGetLastError();
 }
@@ -641,7 +652,7 @@ hipError_t launch_solve_t(hipStream_t s, const SolveWorkspace &w, const DepositT
     if (line.nz > 0) row_lds = std::max(row_lds, sizeof(unsigned long long) * (size_t)kRowThreads);
     hipLaunchKernelGGL((k_rows_fwd<T, FROM_PARTIALS>), dim3(w.nx + (line.nz > 0 ? 1 : 0)),
                        dim3(kRowThreads), row_lds, s, dep, nblocks, q, scale, w.nx, w.ny, w.my,
-                       w.log2_my, (const cx<T> *)w.tw_y, (cx<T> *)w.spec_a, w.pipe, line);
+                       w.log2_my, (const cx<T> *)w.stw_y, (cx<T> *)w.spec_a, w.pipe, line);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_tail<T>(s, w, ex, ey, ef);

@@ -569,11 +569,13 @@ namespace {
 
 // Green's spectrum (open boundary) or the pipe's mode divisors, twiddles and
 // difference factors of a grid, converted to T and copied to the given
-// device tables.
+// device tables (the twiddle tables laid out as SolveWorkspace's stw_x and
+// stw_y: the stage tables hold the plain tables' values, so every FFT
+// multiplies by exactly the twiddles of a plain table).
 // The pipe needs mx = 2 nx and my = 2 ny (its walls sit at node 0 and node
 // n of each axis); the open boundary takes the padded lengths of fft_len.
 template <typename T>
-scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x, void *tw_y,
+scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *stw_x, void *stw_y,
                                 void *sx_t, void *sy_t, bool pipe = false)
 {
     const int nx = grid.nx, ny = grid.ny, mx = fft_len(nx), my = fft_len(ny), hy = my / 2;
@@ -595,8 +597,29 @@ scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x
     }
     for (int l = 0; l <= hy; ++l) sy[l] = (T)(std::sin(2.0 * M_PI * l / my) / grid.dy);
     SCPIC_HIP_TRY(hipMemcpy(ghat_t, g_t.data(), sizeof(T) * g_t.size(), hipMemcpyHostToDevice), "upload ghat");
-    SCPIC_HIP_TRY(hipMemcpy(tw_x, twx.data(), sizeof(T) * twx.size(), hipMemcpyHostToDevice), "upload twiddles");
-    SCPIC_HIP_TRY(hipMemcpy(tw_y, twy.data(), sizeof(T) * twy.size(), hipMemcpyHostToDevice), "upload twiddles");
+    const int lx = ilog2(mx), ly = ilog2(my);
+    std::vector<T> stx(2 * (size_t)mx, T(0)), sty(2 * (size_t)(2 * my + 1), T(0));
+    for (int e = 0; e < stage_twiddle_count(mx, lx); ++e) {
+        const int t = stage_twiddle_exponent(e, mx, lx);
+        stx[2 * e] = twx[2 * t];
+        stx[2 * e + 1] = twx[2 * t + 1];
+    }
+    for (int l = 0; l <= hy; ++l) {
+        sty[2 * l] = twy[2 * l];
+        sty[2 * l + 1] = twy[2 * l + 1];
+    }
+    for (int e = 0; e < stage_twiddle_count(hy, ly - 1); ++e) {
+        const int t = 2 * stage_twiddle_exponent(e, hy, ly - 1);
+        sty[2 * (hy + 1 + e)] = twy[2 * t];
+        sty[2 * (hy + 1 + e) + 1] = twy[2 * t + 1];
+    }
+    for (int e = 0; e < stage_twiddle_count(my, ly); ++e) {
+        const int t = stage_twiddle_exponent(e, my, ly);
+        sty[2 * (my + 1 + e)] = twy[2 * t];
+        sty[2 * (my + 1 + e) + 1] = twy[2 * t + 1];
+    }
+    SCPIC_HIP_TRY(hipMemcpy(stw_x, stx.data(), sizeof(T) * stx.size(), hipMemcpyHostToDevice), "upload twiddles");
+    SCPIC_HIP_TRY(hipMemcpy(stw_y, sty.data(), sizeof(T) * sty.size(), hipMemcpyHostToDevice), "upload twiddles");
     SCPIC_HIP_TRY(hipMemcpy(sx_t, sx.data(), sizeof(T) * sx.size(), hipMemcpyHostToDevice), "upload sx");
     SCPIC_HIP_TRY(hipMemcpy(sy_t, sy.data(), sizeof(T) * sy.size(), hipMemcpyHostToDevice), "upload sy");
     return SCPIC_OK;
@@ -605,7 +628,7 @@ scpic_status upload_grid_tables(const scpic_grid &grid, void *ghat_t, void *tw_x
 template <typename T>
 scpic_status upload_tables(scpic_ctx *c)
 {
-    return upload_grid_tables<T>(c->grid, c->sw.ghat_t, c->sw.tw_x, c->sw.tw_y, c->sw.sx,
+    return upload_grid_tables<T>(c->grid, c->sw.ghat_t, c->sw.stw_x, c->sw.stw_y, c->sw.sx,
                                  c->sw.sy, c->sw.pipe);
 }
 
@@ -650,8 +673,8 @@ scpic_status create_impl(scpic_ctx *c, const scpic_grid *grid, int32_t precision
     c->sw.log2_my = ilog2(my);
     c->sw.mixed = c->mixed;
     c->sw.pipe = false;
-    ALLOC(c->sw.tw_x, ce * mx);
-    ALLOC(c->sw.tw_y, ce * my);
+    ALLOC(c->sw.stw_x, ce * mx);
+    ALLOC(c->sw.stw_y, ce * (2 * (size_t)my + 1));
     ALLOC(c->sw.ghat_t, fe * (size_t)(hy + 1) * mx);
     ALLOC(c->sw.sx, fe * mx);
     ALLOC(c->sw.sy, fe * (hy + 1));
@@ -1211,7 +1234,7 @@ scpic_status batch_layout(scpic_batch *b, int threads, int blocks_per_cu)
 
 struct GridTables {
     scpic_grid grid;
-    void *ghat_t, *tw_x, *tw_y, *sx, *sy;
+    void *ghat_t, *stw_x, *stw_y, *sx, *sy;
 };
 
 scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const int64_t *offsets,
@@ -1280,19 +1303,19 @@ scpic_status batch_create_impl(scpic_batch *b, const scpic_grid *grids, const in
         if (!gt) {
             GridTables t;
             t.grid = gr;
-            BALLOC(t.tw_x, ce * I.mx);
-            BALLOC(t.tw_y, ce * I.my);
+            BALLOC(t.stw_x, ce * I.mx);
+            BALLOC(t.stw_y, ce * (2 * (size_t)I.my + 1));
             BALLOC(t.ghat_t, fe * (size_t)(I.my / 2 + 1) * I.mx);
             BALLOC(t.sx, fe * I.mx);
             BALLOC(t.sy, fe * (I.my / 2 + 1));
-            st = b->mixed ? upload_grid_tables<float>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy)
-                          : upload_grid_tables<double>(gr, t.ghat_t, t.tw_x, t.tw_y, t.sx, t.sy);
+            st = b->mixed ? upload_grid_tables<float>(gr, t.ghat_t, t.stw_x, t.stw_y, t.sx, t.sy)
+                          : upload_grid_tables<double>(gr, t.ghat_t, t.stw_x, t.stw_y, t.sx, t.sy);
             if (st) return st;
             tables.push_back(t);
             gt = &tables.back();
         }
-        I.tw_x = gt->tw_x;
-        I.tw_y = gt->tw_y;
+        I.stw_x = gt->stw_x;
+        I.stw_y = gt->stw_y;
         I.ghat_t = gt->ghat_t;
         I.sx = gt->sx;
         I.sy = gt->sy;

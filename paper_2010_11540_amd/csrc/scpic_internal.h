@@ -99,6 +99,29 @@ struct LineSpec {
     unsigned long long *partial;     // [max_blocks][nz]
 };
 
+// Twiddles of the radix-4 stages of an L-point FFT (L = 2^log2L) as the
+// grid kernels' one-wave Stockham FFT reads them, stage by stage, so that the
+// lanes of a wave read them at consecutive addresses (or all at one): the
+// stage that combines sub-transforms of length ns (ns = 1, 4, 16, ..., or
+// 2, 8, 32, ... after the radix-2 stage of an odd log2L) keeps W^(m span k),
+// W = exp(-2 pi i / L), span = L / (4 ns), for k < ns and m = 1, 2, 3 at entry
+// ns - c + 3 k + m - 1, where c = 1 for even log2L and 2 for odd: L - c
+// entries in all.  stage_twiddle_exponent gives the exponent m span k of
+// entry e.
+__host__ __device__ constexpr int stage_twiddle_count(int L, int log2L)
+{
+    return L - ((log2L & 1) ? 2 : 1);
+}
+inline int stage_twiddle_exponent(int e, int L, int log2L)
+{
+    const int c = (log2L & 1) ? 2 : 1;
+    int ns = c;
+    while (4 * ns - c <= e) ns *= 4;
+    const int r = e - (ns - c);
+    const int k = r / 3, m = r - 3 * k + 1;
+    return m * (L / (4 * ns)) * k;
+}
+
 // Most nodes of a line-density grid.
 constexpr int kMaxLineNodes = 512;
 
@@ -113,7 +136,7 @@ struct BatchInstance {
     DepositTarget dep;                 // max_blocks == pass_blocks
     int32_t nx, ny, mx, my, log2_mx, log2_my;
     double scale;                      // 1 / (2^24 N0): charge units -> rho
-    const void *tw_x, *tw_y, *ghat_t, *sx, *sy;
+    const void *stw_x, *stw_y, *ghat_t, *sx, *sy;  // twiddle tables as in SolveWorkspace
     void *spec_a, *spec_bx, *spec_by;
     void *ef;                          // interleaved node field
 };
@@ -180,7 +203,11 @@ struct SolveWorkspace {
     int nx, ny, mx, my, log2_mx, log2_my;  // mx, my: FFT lengths, powers of two >= 2n
     bool mixed;
     bool pipe;           // grounded rectangular pipe instead of the open boundary
-    void *tw_x, *tw_y;   // [mx], [my] complex twiddles exp(-2 pi i t / m)
+    // complex twiddle tables: stw_x the stage twiddles of the mx-point FFT
+    // [mx]; stw_y the plain exp(-2 pi i l / my) for l = 0..hy, then the stage
+    // twiddles of the hy-point FFT at hy + 1 and of the my-point FFT at my + 1
+    // [2 my + 1]
+    void *stw_x, *stw_y;
     void *ghat_t;        // [my/2+1][mx] real Green's spectrum / (mx my), transposed
     void *sx, *sy;       // [mx] sin(2 pi k / mx)/dx, [my/2+1] sin(2 pi l / my)/dy
     void *spec_a;        // [my/2+1][nx] complex, rows transformed
