@@ -645,8 +645,26 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
 
     const bool moves = KICK || els.n_el > 0;
     int bi0 = INT_MAX, bi1 = -1, bj0 = INT_MAX, bj1 = -1, cnt = 0;
+    // The streamed form keeps two particles in flight per lane ahead of the
+    // one worked on (its loads come from memory, not the last-level cache):
+    // the second is loaded here and moves up each iteration.
+    static_assert(!NT || !SIX, "the streamed pass is four-dimensional");
+    double xa = 0, pxa = 0, ya = 0, pya = 0;
+    float wa = 1.0f;
+    uint8_t lfa = 1;
+    if constexpr (NT) {
+        const int64_t pa = p + T;
+        if (pa < P.n) {
+            xa = __builtin_nontemporal_load(&P.x[pa]);
+            pxa = __builtin_nontemporal_load(&P.px[pa]);
+            ya = __builtin_nontemporal_load(&P.y[pa]);
+            pya = __builtin_nontemporal_load(&P.py[pa]);
+            lfa = P.lost ? P.lost[pa] : 0;
+            if (KICK && P.w) wa = P.w[pa];
+        }
+    }
     for (; p < P.n; p += T) {
-        const int64_t pn = p + T;
+        const int64_t pn = p + (NT ? 2 : 1) * T;
         double xn = 0, pxn = 0, yn = 0, pyn = 0, sgn = 0, psgn = 0;
         float wn = 1.0f;
         uint8_t lfn = 1;
@@ -774,16 +792,31 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
                 }
             }
         }
-        x = xn;
-        px = pxn;
-        y = yn;
-        py = pyn;
-        if constexpr (SIX) {
-            sg = sgn;
-            psg = psgn;
+        if constexpr (NT) {
+            x = xa;
+            px = pxa;
+            y = ya;
+            py = pya;
+            wp = wa;
+            lf = lfa;
+            xa = xn;
+            pxa = pxn;
+            ya = yn;
+            pya = pyn;
+            wa = wn;
+            lfa = lfn;
+        } else {
+            x = xn;
+            px = pxn;
+            y = yn;
+            py = pyn;
+            if constexpr (SIX) {
+                sg = sgn;
+                psg = psgn;
+            }
+            wp = wn;
+            lf = lfn;
         }
-        wp = wn;
-        lf = lfn;
     }
 
     if constexpr (DEPOSIT) {
