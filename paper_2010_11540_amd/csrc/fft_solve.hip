@@ -393,14 +393,13 @@ __global__ void __launch_bounds__(kRowThreads)
 // Every beam of a batch: workgroup -> (beam, row) from the batch's row table;
 // the rows come from the partials of the beam's last batched pass.  A beam's
 // row has few partial slices, so a smaller workgroup does it and more of them
-// fit on a compute unit at once.
-constexpr int kBatchRowThreads = 256;
-
-template <typename T>
-__global__ void __launch_bounds__(kBatchRowThreads) k_rows_fwd_batched(BatchLaunch b)
+// fit on a compute unit at once: NT threads, at least the largest ny and hy
+// of the batch (128 when every beam's grid has ny <= 128, else 256).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_rows_fwd_batched(BatchLaunch b)
 {
     const BatchInstance &I = b.inst[b.row_inst[blockIdx.x]];
-    rows_fwd_body<T, true, kBatchRowThreads>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
+    rows_fwd_body<T, true, NT>(I.dep, I.pass_blocks, nullptr, I.scale, I.nx, I.ny,
                                              I.my, I.log2_my, (const cx<T> *)I.stw_y,
                                              (cx<T> *)I.spec_a, (int)blockIdx.x - I.row_block0,
                                              false);
@@ -667,7 +666,10 @@ hipError_t launch_solve_batched_t(hipStream_t s, const BatchLaunch &b, int rows,
                            sizeof(BlockHeader) * (size_t)std::max(max_pass_blocks, 1);
     const size_t col_lds = 5 * sizeof(cx<T>) * (size_t)mmx;
     const size_t inv_lds = 3 * sizeof(cx<T>) * (size_t)mmy;
-    hipLaunchKernelGGL(k_rows_fwd_batched<T>, dim3(rows), dim3(kBatchRowThreads), row_lds, s, b);
+    if (max_ny <= 128 && mmy / 2 <= 128)
+        hipLaunchKernelGGL((k_rows_fwd_batched<T, 128>), dim3(rows), dim3(128), row_lds, s, b);
+    else
+        hipLaunchKernelGGL((k_rows_fwd_batched<T, 256>), dim3(rows), dim3(256), row_lds, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cols_batched<T>, dim3(cols), dim3(kColThreads), col_lds, s, b);

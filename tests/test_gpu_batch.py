@@ -92,6 +92,34 @@ def test_batch_equals_single_beam_path(gpu, precision):
         np.testing.assert_array_equal(fields[k][1], ey, err_msg=f"beam {k} ey")
 
 
+def test_batch_with_a_wide_grid_equals_single_beam_path(gpu):
+    """A batch whose widest grid has ny > 128 (a 64 x 256 grid beside a 64^2
+    one) runs its row kernel on wider workgroups than a batch of grids up to
+    128 wide; both beams still equal their single-beam runs bit for bit."""
+    _say("batch with a 64x256 grid, 2 turns fp64: batched == single-beam, bit-exact")
+    kappa = inputs.kappa_for_tune_shift(-0.2, 1e-6, 16)
+    grids = [inputs.make_grid(64), inputs.make_grid(64, 256, 6e-3, 6e-3)]
+    lattices = [inputs.ring(4.2, 4.3, 16, kappa), inputs.ring(4.12, 4.27, 16, kappa)]
+    beams = [inputs.gaussian_beam(n, 700 + k) for k, n in enumerate((6000, 9000))]
+    parts, offsets = inputs.concat_parts(beams)
+    with gpu.Batch(grids, offsets) as b:
+        d = _dev(parts)
+        b.track(d, lattices, 2)
+        got = _host(d)
+        fields = [tuple(t.cpu().numpy() for t in b.get_field(k)) for k in range(len(grids))]
+    for k in range(len(grids)):
+        with gpu.Context(grids[k]) as ctx:
+            dk = _dev(_beam(parts, offsets, k))
+            ctx.track(dk, lattices[k], 2)
+            want = _host(dk)
+            ex, ey = (t.cpu().numpy() for t in ctx.get_field())
+        mine = _beam(got, offsets, k)
+        for key in COORDS + ("lost",):
+            np.testing.assert_array_equal(mine[key], want[key], err_msg=f"beam {k} {key}")
+        np.testing.assert_array_equal(fields[k][0], ex, err_msg=f"beam {k} ex")
+        np.testing.assert_array_equal(fields[k][1], ey, err_msg=f"beam {k} ey")
+
+
 def test_batch_one_turn_matches_oracle(gpu, orc):
     _say("batch of 6 beams, 1 turn fp64 vs oracle")
     parts, offsets, grids, lattices = _mixed_batch()
