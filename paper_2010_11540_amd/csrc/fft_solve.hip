@@ -4,7 +4,9 @@
 // method), the centred-difference field taken in the spectrum.  Each axis is
 // padded to the power of two mx >= 2 nx (my >= 2 ny): any such length makes
 // the cyclic convolution equal the linear one on nodes -1..n.  Hand-written
-// radix-4/2 Stockham FFTs in LDS; no vendor FFT library.
+// radix-4/2 Stockham FFTs in LDS, each run by one wave, reading per-stage
+// twiddle tables and XOR-swizzled buffers so that no stage's LDS accesses
+// conflict on banks; no vendor FFT library.
 //
 // Data flow for a charge grid q (nx x ny, rows i along x; hy = my / 2):
 //   k_rows_fwd   one workgroup per row i: sum the row's partials exactly
