@@ -472,8 +472,8 @@ __device__ __forceinline__ Box charge_tile(const GridGeom &g, const BlockHeader 
 // The fused particle pass.  Thread t of the launch (T threads in all) walks
 // the particles p = t, t+T, t+2T, ...: consecutive lanes take consecutive
 // particles, so every SoA load and store is coalesced, and the next
-// particle's loads are issued before the current one is worked on.  For each
-// particle:
+// particle's loads (the next two in the streamed form) are issued before the
+// current one is worked on.  For each particle:
 //   KICK     gather the node field at the particle with the deposit weights
 //            and kick px, py by kappa * w_p * E (w_p = 1 without weights);
 //            a particle found outside the domain is marked lost and frozen;
