@@ -601,6 +601,28 @@ __device__ __forceinline__ void pass_body(const ParticlePtrs &P, const GridGeom 
     if constexpr (KICK) {
         ebox = fbox;
         staged = field_bytes && field_bytes + tile_bytes <= (size_t)lds_bytes;
+        if (field_bytes && !staged && tile_bytes < (size_t)lds_bytes) {
+            // The whole box does not fit beside the tile: stage its centre,
+            // as much as fits, when that keeps at least half of its nodes
+            // (the box's edges hold only the tails of the distribution; a
+            // particle outside the staged part gathers from L2).
+            const int64_t room = (int64_t)(((size_t)lds_bytes - tile_bytes) / sizeof(V)) - 2;
+            if (2 * room >= (int64_t)fbox.h * fbox.w) {
+                int i0 = fbox.i0, i1 = fbox.i0 + fbox.h - 1, j0 = fbox.j0, j1 = fbox.j0 + fbox.w - 1;
+                while ((int64_t)(i1 - i0 + 1) * (j1 - j0 + 1) > room) {
+                    // trim the longer side, one node at each end
+                    if (i1 - i0 >= j1 - j0) {
+                        ++i0;
+                        --i1;
+                    } else {
+                        ++j0;
+                        --j1;
+                    }
+                }
+                ebox = Box{i0, j0, i1 - i0 + 1, j1 - j0 + 1};
+                staged = ebox.h >= 2 && ebox.w >= 2;
+            }
+        }
         if (staged) {
             // four nodes per thread per round; indices past the box repeat
             // its last node, so every load and store is unconditional and
