@@ -30,6 +30,11 @@
 
 #include "scpic_internal.h"
 
+// The solve carries no bit-exactness contract (its field is compared with the
+// direct-sum solve within a tolerance, and the batched and single-beam paths
+// share this code): multiply-adds may be fused here, unlike in the pass.
+#pragma clang fp contract(fast)
+
 namespace scpic {
 namespace {
 
