@@ -127,8 +127,11 @@ typedef struct {
  *                       sextupole of the same gamma0 may be folded into its
  *                       first or last H0 flow, which the exact flows allow)
  * The thick elements need the particles' sigma and psigma and are evaluated in
- * FP64 with the device's sin, cos, expm1 and sqrt (results agree with any
- * other correctly implemented evaluation to rounding, not bit for bit).
+ * FP64: the on-momentum angles' sin, cos, sinh and cosh and the sextupole's
+ * step lengths once per element on the host, each particle's chromatic
+ * correction by series and angle doubling and its sqrt(1 - p_sigma) on the
+ * device (results agree with any other correctly implemented evaluation to
+ * rounding, not bit for bit).
  * Linear maps are evaluated as written in row order, left to right, with no
  * fused multiply-add, so a push is bit-identical to the same sums in IEEE
  * FP64.  sizeof(scpic_element) == 136. */

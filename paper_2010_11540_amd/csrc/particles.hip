@@ -308,7 +308,8 @@ __device__ __forceinline__ void quad_thick(const double *__restrict__ m, double 
 // V = k2 (x^3 - 3 x y^2)/6 over the step h = L/n:
 //   H0 (a h), V (h/2), H0 (c h), V (h/2), H0 (a h),  c = 1/sqrt 3, a = (1 - c)/2.
 // k2 = 0 takes the drift in one step; m[4] and m[5] are drift lengths the
-// host folded into the first and last H0 flow.  p_sigma is constant in every
+// host folded into the first and last H0 flow, m[6..9] the step lengths it
+// derived (the same for every particle).  p_sigma is constant in every
 // element.
 __device__ __forceinline__ void apply_element6(int kind, const double *__restrict__ m, double &x,
                                                double &px, double &y, double &py, double &sg,
@@ -318,17 +319,17 @@ __device__ __forceinline__ void apply_element6(int kind, const double *__restric
         quad_thick(m, x, px, y, py, sg, k);
     } else if (kind == SCPIC_EL_SEXT_THICK && m[0] == 0.0) {
         // no sextupole field: the split composes to the exact drift of H0
-        const double L = m[1] + m[4] + m[5];
+        // over the whole length m[1] + m[4] + m[5], which the host put in m[6]
+        const double L = m[6];
         sg = fma(fma(-0.5 * px, px, fma(-0.5 * py, py, k.psg * m[2])), L, sg);
         x = fma(px * k.q, L, x);
         y = fma(py * k.q, L, y);
     } else if (kind == SCPIC_EL_SEXT_THICK) {
-        constexpr double kC = 0.57735026918962576451;  // 1/sqrt(3)
-        constexpr double kA = 0.5 * (1.0 - kC);
+        // the step h = m[1] / n and the split's a h, c h, k2 h / 2, computed
+        // by the host in m[6..9]
         const int n = (int)m[3];
-        const double h = m[1] / (double)n;
         const double dsg = k.psg * m[2];
-        const double ta = kA * h, tc = kC * h, tv = 0.5 * h * m[0];
+        const double ta = m[7], tc = m[8], tv = m[9];
         auto drift = [&](double t) {
             x = fma(px * k.q, t, x);
             y = fma(py * k.q, t, y);

@@ -264,7 +264,8 @@ scpic_status check_longitudinal(const std::vector<const scpic_element *> &els,
 // 1/gamma0^2 is folded into that sextupole's first or last H0 flow, and
 // adjacent drifts into one: the exact flows of H0 compose by adding their
 // lengths, so this changes results only by rounding.  A thick sextupole's
-// p[4] and p[5] carry the folded lead-in and tail lengths.
+// p[4] and p[5] carry the folded lead-in and tail lengths, p[6..9] its step
+// lengths.
 PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, size_t end)
 {
     PassElements pe;
@@ -313,6 +314,25 @@ PassElements pack(const std::vector<const scpic_element *> &v, size_t begin, siz
         ++k;
     }
     pe.n_el = k;
+    // A thick sextupole's step lengths, the same for every particle, once
+    // here (after the folding above, which changes p[1], p[4], p[5]) and with
+    // the same operations the kernel would apply: p[6] = L / n and the
+    // split's a h, c h and k2 h / 2 in p[7..9]; a drift's whole length in p[6].
+    for (int e = 0; e < k; ++e) {
+        if (pe.kind[e] != SCPIC_EL_SEXT_THICK) continue;
+        double *q = pe.p[e];
+        if (q[0] == 0.0) {
+            q[6] = q[1] + q[4] + q[5];
+        } else {
+            constexpr double kC = 0.57735026918962576451;  // 1/sqrt(3)
+            constexpr double kA = 0.5 * (1.0 - kC);
+            const double h = q[1] / (double)(int)q[3];
+            q[6] = h;
+            q[7] = kA * h;
+            q[8] = kC * h;
+            q[9] = 0.5 * h * q[0];
+        }
+    }
     return pe;
 }
 
