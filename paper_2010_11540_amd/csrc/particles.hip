@@ -227,8 +227,17 @@ __device__ __forceinline__ Chroma chroma(double psg)
     Chroma k;
     k.psg = psg;
     k.q = 1.0 - psg;
-    k.sq = sqrt(k.q);
-    k.isq = 1.0 / k.sq;
+    // 1/sqrt(q) from the hardware estimate and two Newton steps (each about
+    // doubles the correct bits), then sqrt(q) = q / sqrt(q): within a unit or
+    // two of the last place, in a third of the instructions of a correctly
+    // rounded square root and division (the thick elements carry no
+    // bit-exactness contract; q <= 0 gives NaN either way)
+    double y = __builtin_amdgcn_rsq(k.q);
+    const double hq = -0.5 * k.q;
+    y = y * fma(hq * y, y, 1.5);
+    y = y * fma(hq * y, y, 1.5);
+    k.isq = y;
+    k.sq = k.q * y;
     return k;
 }
 
